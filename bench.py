@@ -1,0 +1,209 @@
+"""Benchmark: observed-entry SGLD updates/s of the PSGLD sampler on one MI355X.
+
+Workload (default): recommender-shaped sparse Gaussian MF, I = 70,000 rows,
+J = 10,700 columns, 10M observed ratings (9M training, 1M held out), fit
+K = 50, B = 32, T = 1000 iterations with burn-in 500 and moments kept every
+10th post-burn-in iteration.  A step is one PSGLD iteration (one part).
+
+The timed region is one psgld_step call of K iterations from t = 0 (the
+chain's state after the warmup is rolled back), with the data resident in
+HBM.  value = training entries visited / elapsed seconds.  A second pass
+replays the same iterations with HIP events around every launch to get the
+sampler kernel's average duration, from which the roofline fraction is
+computed with the algorithmic bytes of each iteration.  The FP64 oracle is
+timed on the host on a bounded sample (cpu_baseline).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "observed-entry SGLD updates/s at matched held-out RMSE; served-job p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+class HipEvents:
+    """hipEvent timing on a given stream, through the HIP runtime's C API."""
+
+    def __init__(self):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def create(self, n):
+        evs = []
+        for _ in range(n):
+            e = C.c_void_p()
+            assert self.hip.hipEventCreate(C.byref(e)) == 0
+            evs.append(e)
+        return evs
+
+    def record(self, ev, stream):
+        assert self.hip.hipEventRecord(ev, C.c_void_p(stream)) == 0
+
+    def elapsed_ms(self, a, b):
+        assert self.hip.hipEventSynchronize(b) == 0
+        ms = C.c_float()
+        assert self.hip.hipEventElapsedTime(C.byref(ms), a, b) == 0
+        return float(ms.value)
+
+    def sync(self):
+        assert self.hip.hipDeviceSynchronize() == 0
+
+
+def algorithmic_bytes(wl, n_p, ho_p, t):
+    """Bytes one iteration must move at minimum: each training entry of the
+    part read once (4-byte index + 4-byte value), every factor element read
+    and written once in FP32, the FP64 sums of x and x^2 read and written at
+    kept iterations, one FP64 read-modify-write per held-out cell of the part
+    after burn-in."""
+    p = t % wl.B
+    b = 8 * n_p[p] + 8 * (wl.I + wl.J) * wl.K
+    if t >= wl.burn_in:
+        b += 16 * ho_p[p]
+        if (t - wl.burn_in) % wl.thin == 0:
+            b += 32 * (wl.I + wl.J) * wl.K
+    return b
+
+
+def make_workload(name):
+    if name == "sparse_ratings_70k":
+        wl = workloads.sparse_ratings()
+        wl.thin = 10
+        return wl
+    if name == "dense_poisson_256":
+        return workloads.dense_poisson()
+    if name == "sparse_ratings_small":
+        wl = workloads.sparse_ratings(I=7000, J=1070, nnz=1_000_000, B=32, name=name)
+        wl.thin = 10
+        return wl
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, iters):
+    import oracle
+    cfg = oracle.Config(**wl.fit_kwargs())
+    ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+    n_p = ch.part_sizes()
+    t0 = time.perf_counter()
+    ch.run(iters)
+    dt = time.perf_counter() - t0
+    entries = int(sum(n_p[t % wl.B] for t in range(iters)))
+    return {"value": entries / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations from t=0 ({iters / wl.B:g} cycles of the {wl.B} parts) "
+                      f"of the same workload, single-threaded FP64 C, {dt:.1f} s incl. its setup"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="sparse_ratings_70k")
+    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1506_01418_amd as pkg
+
+    t_gen = time.perf_counter()
+    wl = make_workload(args.workload)
+    print(f"[bench] workload {wl.name}: I={wl.I} J={wl.J} nnz={wl.nnz} K={wl.K} B={wl.B} "
+          f"({time.perf_counter() - t_gen:.1f} s to generate)", file=sys.stderr, flush=True)
+
+    ev = HipEvents()
+    s = pkg.PSGLD.from_workload(wl)
+    stream = s.stream()
+    n_p, N = s.part_sizes()
+    ho_part = (np.asarray(pkg_pieces(wl, "col"))[wl.hcol] - np.asarray(pkg_pieces(wl, "row"))[wl.hrow]) % wl.B
+    ho_p = np.bincount(ho_part, minlength=wl.B)
+    state0 = s.get_state()
+
+    # warmup, then roll the chain back to t = 0
+    s.step(args.warmup, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    s.sync()
+    s.set_state(state0)
+    ev.sync()
+
+    # pass 1: whole-job throughput, one call of K iterations
+    e0, e1 = ev.create(2)
+    ev.record(e0, stream)
+    s.step(args.steps, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    ev.record(e1, stream)
+    elapsed_ms = ev.elapsed_ms(e0, e1)
+    s.sync()
+    ev.sync()
+    entries = int(sum(n_p[t % wl.B] for t in range(args.steps)))
+    value = entries / (elapsed_ms * 1e-3)
+    rmse = s.heldout_rmse() if args.steps > wl.burn_in else None
+    print(f"[bench] pass 1: {args.steps} iterations in {elapsed_ms:.3f} ms, "
+          f"{value:.4g} updates/s, held-out RMSE {rmse}", file=sys.stderr, flush=True)
+
+    # pass 2: the same iterations again, HIP events around every launch
+    s.set_state(state0)
+    ev.sync()
+    evs = ev.create(2 * args.steps)
+    for t in range(args.steps):
+        ev.record(evs[2 * t], stream)
+        s.step(1, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        ev.record(evs[2 * t + 1], stream)
+    durs = np.array([ev.elapsed_ms(evs[2 * t], evs[2 * t + 1]) for t in range(args.steps)])
+    s.sync()
+    rmse2 = s.heldout_rmse() if args.steps > wl.burn_in else None
+    alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
+    avg_ms = float(durs.mean())
+    achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
+    print(f"[bench] pass 2: kernel avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic, "
+          f"RMSE {rmse2}", file=sys.stderr, flush=True)
+    s.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_iters)
+        print(f"[bench] oracle: {cpu['value']:.4g} updates/s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
+                   "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
+                   "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
+                   "heldout_rmse": rmse, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sparse_iter_kernel", "avg_launch_us": avg_ms * 1e3,
+                     "alg_bytes_per_launch": float(alg.mean())},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def pkg_pieces(wl, which):
+    n = wl.I if which == "row" else wl.J
+    return np.concatenate([np.full(len(a), b) for b, a in enumerate(np.array_split(np.arange(n), wl.B))])
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * psgld.h -- C ABI of an MI355X (gfx950) library for Parallel SGLD (PSGLD)
+ * matrix factorisation, after Simsekli et al., "Parallel Stochastic Gradient
+ * Markov Chain Monte Carlo for Matrix Factorisation Models" (arXiv:1506.01418).
+ *
+ * Model (Section 2, Eq. (1); Section 4, Eq. (13)): V (I x J) ~ W H with W
+ * (I x K) and H (K x J); v_ij ~ Tweedie(mean sum_k w_ik h_kj, dispersion phi,
+ * power parameter beta), whose log density is -d_beta(v||mu)/phi up to a
+ * constant; iid exponential or Gaussian priors on every factor element.
+ *
+ * Sampler (Section 3, Eq. (7)-(9), Algorithm 1): [I] and [J] are each cut
+ * into B pieces; block (b, c) is the cross product of row piece b and column
+ * piece c (Definition 1); iteration t uses part p = t mod B, made of blocks
+ * (b, (b + p) mod B) for b = 0..B-1 (Definition 2, cyclic order as in the
+ * experiments of Section 4.2.1).  Every element x of W and H moves by
+ *     x <- x + eps_t (N/|Pi_t| * sum over its block's entries of
+ *                     d log p(v_ij | .)/dx + d log p(x)/dx) + sqrt(2 eps_t) z
+ * with both gradients at the previous state, z ~ N(0,1), then x <- |x| when
+ * mirroring is on (Section 3.2).  N is the number of observed training
+ * entries and |Pi_t| the number of them in the part.
+ *
+ * Conventions of the whole ABI:
+ *  - Every call returns a psgld_status (0 = OK, negative = error) except
+ *    psgld_last_error, psgld_destroy and psgld_default_options.  No exception
+ *    crosses the ABI.  After an error, psgld_last_error(ctx) describes it
+ *    until the next call on that ctx.
+ *  - All array arguments are HOST pointers owned by the caller; the library
+ *    copies what it needs during the call and never keeps the pointer.
+ *    Output arrays are caller-allocated with the sizes stated below.
+ *  - W is exchanged as I x K row-major and H as K x J row-major (the paper's
+ *    orientation), in the precision named in each signature.
+ *  - The library owns the context and all device memory it allocates.
+ *  - A context is used by one host thread at a time.  Stepping is
+ *    asynchronous on the context's stream; getters synchronise it.
+ */
+#ifndef PSGLD_H
+#define PSGLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSGLD_OK = 0,
+    PSGLD_E_ARG = -1,         /* invalid argument or data (message says which) */
+    PSGLD_E_STATE = -2,       /* call not valid in the context's current state */
+    PSGLD_E_NOMEM = -3,       /* host or device allocation failed */
+    PSGLD_E_DEVICE = -4,      /* HIP runtime error, or no gfx950 device */
+    PSGLD_E_NUMERIC = -5,     /* a non-finite value appeared in W or H */
+    PSGLD_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} psgld_status;
+
+typedef struct psgld_ctx psgld_ctx;
+
+/* Tweedie likelihood, Section 4: beta = 2 Gaussian, 1 Poisson, 0 < beta < 1
+ * compound Poisson, 0 gamma.  phi > 0.  For beta < 2 the mean is floored at
+ * options.mu_floor before the residual (v - mu) mu^(beta-2) / phi. */
+typedef struct {
+    double beta;
+    double phi;
+} psgld_likelihood;
+
+typedef enum {
+    PSGLD_PRIOR_EXPONENTIAL = 0,  /* rate lambda, density on |x| (Eq. (13)) */
+    PSGLD_PRIOR_GAUSSIAN = 1      /* mean 0, precision lambda */
+} psgld_prior_kind;
+
+typedef struct {
+    int32_t kind;       /* psgld_prior_kind */
+    double lambda_w;    /* > 0 */
+    double lambda_h;    /* > 0 */
+    int32_t mirror;     /* 1: x <- |x| after each update (Algorithm 1) */
+} psgld_prior;
+
+/* Step size eps_t = a * (t0 + t)^(-gamma) at the 0-based global iteration t
+ * (the paper's (a/t)^b is a = a^b, t0 = 1, gamma = b).  Eq. (4) asks for
+ * gamma in (0.5, 1]; gamma = 0 (a constant step) is accepted too. */
+typedef struct {
+    double a;
+    double t0;
+    double gamma;
+} psgld_eps_schedule;
+
+enum { PSGLD_FP32 = 0, PSGLD_BF16_DENSE = 1 };
+enum {
+    PSGLD_TEST_NOISE_OFF = 1u,  /* z = 0: the chain becomes parallel SGD */
+    PSGLD_TEST_FREEZE_W = 2u,   /* W is not updated */
+    PSGLD_TEST_FREEZE_H = 4u    /* H is not updated */
+};
+
+typedef struct {
+    uint64_t seed;            /* Philox key of the Langevin noise */
+    int64_t burn_in;          /* moments and held-out sums start at t >= burn_in */
+    int32_t thin;             /* moments kept at t - burn_in = 0, thin, 2 thin, ... */
+    int32_t precision;        /* PSGLD_FP32 or PSGLD_BF16_DENSE (dense blocks only) */
+    double dense_threshold;   /* blocks denser than this use the dense kernel */
+    double mu_floor;          /* floor of the Tweedie mean when beta < 2 */
+    const int32_t *row_piece; /* optional, length I: piece of each row; NULL = contiguous split */
+    const int32_t *col_piece; /* optional, length J: piece of each column */
+    void *stream;             /* hipStream_t to run on; NULL = the library's own stream */
+    uint32_t test_flags;      /* PSGLD_TEST_* (test use only) */
+    int32_t device;           /* HIP device ordinal */
+} psgld_options;
+
+/* Fills *opt with the defaults: seed 0, burn_in 0, thin 1, FP32,
+ * dense_threshold 0.3, mu_floor 1e-6, contiguous pieces, own stream,
+ * no test flags, device 0. */
+void psgld_default_options(psgld_options *opt);
+
+/* Creates a context for an I x J matrix, rank K (1..256), B x B blocks
+ * (1 <= B <= min(I, J)).  opt may be NULL for the defaults; it is copied.
+ * Pieces given in opt must be non-empty for every b (Section 3, P_B).
+ * E_ARG on invalid sizes or parameters (phi, lambda > 0, thin >= 1).
+ * No device memory is allocated until data is loaded. */
+psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B,
+                          const psgld_likelihood *lik, const psgld_prior *prior,
+                          const psgld_options *opt, psgld_ctx **out);
+
+/* Loads the observed TRAINING entries (Algorithm 1 input V) as coordinates:
+ * row[n] in [0, I), col[n] in [0, J), val[n] finite, with val >= 0 when
+ * beta <= 1 and val > 0 when beta <= 0.  Cells absent from the list are
+ * missing (not zero).  Duplicated (row, col) pairs are E_ARG.  Builds the
+ * block-sorted layout on the host and uploads it.  Once per context
+ * (E_STATE on a second load).  nnz >= 0 and below 2^31. */
+psgld_status psgld_load_coo(psgld_ctx *ctx, int64_t nnz, const int32_t *row,
+                            const int32_t *col, const float *val);
+
+/* Loads a dense I x J row-major value matrix V with a training mask
+ * (1 = observed training cell, 0 = missing; NULL = every cell observed).
+ * Blocks whose training density exceeds options.dense_threshold are run by
+ * the dense kernel, the rest as coordinates.  Same value rules as load_coo. */
+psgld_status psgld_load_dense(psgld_ctx *ctx, const float *V, const uint8_t *train_mask);
+
+/* Held-out cells whose posterior-mean prediction is tracked: at every
+ * iteration t >= burn_in whose part contains the cell's block, mu_ij of the
+ * state entering that iteration is added to the cell's FP64 sum.  Cells
+ * must be distinct and must not be training entries (E_STATE).  Call after
+ * a load and before the first step.  val may be NULL (then heldout_rmse is
+ * unavailable). */
+psgld_status psgld_load_heldout(psgld_ctx *ctx, int64_t n, const int32_t *row,
+                                const int32_t *col, const float *val);
+
+/* Sets the current sample: W is I x K, H is K x J, finite.  With mirroring
+ * on, |W| and |H| are stored.  Required before the first step (Algorithm 1
+ * takes W(0), H(0) as inputs). */
+psgld_status psgld_set_factors(psgld_ctx *ctx, const float *W, const float *H);
+
+/* Runs n_iter >= 0 iterations of Algorithm 1, asynchronously on the
+ * context's stream, continuing from the context's iteration counter t.
+ * E_STATE before data and factors are set.  A non-finite value produced by
+ * these iterations is reported as E_NUMERIC by the next synchronising call. */
+psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule *sched);
+
+/* Blocks until the context's queued work is done.  E_NUMERIC (with the
+ * first iteration index in the message) if a non-finite value appeared. */
+psgld_status psgld_sync(psgld_ctx *ctx);
+
+/* Copies the current sample out (FP32): W is I x K, H is K x J.  Syncs. */
+psgld_status psgld_get_factors(psgld_ctx *ctx, float *W, float *H);
+
+/* Posterior mean and plug-in variance sum(x^2)/S - mean^2 over the S kept
+ * samples (FP64 sums kept on the device).  E_STATE if S = 0.  Syncs. */
+psgld_status psgld_posterior_mean(psgld_ctx *ctx, double *W, double *H);
+psgld_status psgld_posterior_var(psgld_ctx *ctx, double *W, double *H);
+
+/* Number of kept samples S so far. */
+psgld_status psgld_num_samples(psgld_ctx *ctx, int64_t *S);
+
+/* Posterior-mean prediction of each held-out cell, in load order (n values):
+ * the average of mu_ij over the iterations that visited its block after
+ * burn-in.  Cells not visited yet give NaN.  Syncs. */
+psgld_status psgld_heldout_predictions(psgld_ctx *ctx, double *pred);
+
+/* Root mean squared error of those predictions against the held-out values,
+ * unclipped.  E_STATE if no held-out values were given or none visited. */
+psgld_status psgld_heldout_rmse(psgld_ctx *ctx, double *rmse);
+
+/* Training log-likelihood of the current sample, -sum d_beta(v||mu)/phi over
+ * the training entries (the Tweedie normaliser, free of W and H, dropped),
+ * reduced in FP64 on the device.  Syncs. */
+psgld_status psgld_log_likelihood(psgld_ctx *ctx, double *ll);
+
+/* Iteration counter t (number of iterations run so far). */
+psgld_status psgld_iteration(psgld_ctx *ctx, int64_t *t);
+
+/* |Pi_p| for p = 0..B-1 (training entries in each part), and N. */
+psgld_status psgld_part_sizes(psgld_ctx *ctx, int64_t *n_p, int64_t *N);
+
+/* Checkpoint.  get_state with buf == NULL stores the needed size in *size;
+ * otherwise writes the chain state (t, W, H, moments, held-out sums) into
+ * buf of *size bytes.  set_state restores it into a context created and
+ * loaded identically; since the noise is keyed by (seed, t, index), a
+ * restored chain continues bit for bit. */
+psgld_status psgld_get_state(psgld_ctx *ctx, void *buf, size_t *size);
+psgld_status psgld_set_state(psgld_ctx *ctx, const void *buf, size_t size);
+
+/* Device memory held by the context, in bytes. */
+psgld_status psgld_memory_bytes(psgld_ctx *ctx, int64_t *bytes);
+
+/* The hipStream_t the context runs on. */
+psgld_status psgld_get_stream(psgld_ctx *ctx, void **stream);
+
+/* Message of the context's last error ("" if none).  ctx may be NULL, then
+ * the message of the last failed psgld_create on this thread. */
+const char *psgld_last_error(const psgld_ctx *ctx);
+
+/* Frees the context and its device memory.  NULL is ignored. */
+void psgld_destroy(psgld_ctx *ctx);
+
+/* ---- noise stream (Section 2: noise N(0, 2 eps) per parameter) ----------
+ * The Langevin noise of parameter k of row i of W (stream 0) or column j of
+ * H (stream 1) at iteration t is z = Box-Muller(Philox4x32-10(counter =
+ * (k/4, index, t, stream), key = (seed lo, seed hi))) component k mod 4,
+ * uniforms u = (2 (r >> 9) + 1) 2^-24.  These two calls evaluate the stream
+ * on the device for n counters given on the host, so tests can compare it
+ * with an independent implementation. */
+
+/* out[4n]: raw Philox4x32-10 blocks of ctr[4n] under key[2n]. */
+psgld_status psgld_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key,
+                                 uint32_t *out, int32_t device);
+
+/* z[K n], radius[K n]: the K normals of rows/columns index[n] of stream
+ * stream[n] at iteration t[n] under `seed`, as the sampler draws them. */
+psgld_status psgld_normals(int64_t n, uint64_t seed, const int64_t *t, const uint32_t *stream,
+                           const int64_t *index, int32_t K, float *z, float *radius,
+                           int32_t device);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSGLD_H */

@@ -1,0 +1,398 @@
+"""Python binding of libpsgld, the MI355X (gfx950) Parallel SGLD library.
+
+The functions here carry the names of the C ABI in ``include/psgld.h`` and
+only marshal arguments: every step of the sampler runs in the HIP kernels of
+``libpsgld.so``.  There is no CPU fallback: if the library has not been built
+(``python -m paper_1506_01418_amd.build``) importing this package fails.
+
+``PSGLD`` is a thin convenience wrapper around one context.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsgld.so")
+
+PSGLD_OK = 0
+PSGLD_E_ARG = -1
+PSGLD_E_STATE = -2
+PSGLD_E_NOMEM = -3
+PSGLD_E_DEVICE = -4
+PSGLD_E_NUMERIC = -5
+PSGLD_E_UNSUPPORTED = -6
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_NOMEM", -4: "E_DEVICE",
+                -5: "E_NUMERIC", -6: "E_UNSUPPORTED"}
+
+PSGLD_PRIOR_EXPONENTIAL = 0
+PSGLD_PRIOR_GAUSSIAN = 1
+PSGLD_FP32 = 0
+PSGLD_BF16_DENSE = 1
+PSGLD_TEST_NOISE_OFF = 1
+PSGLD_TEST_FREEZE_W = 2
+PSGLD_TEST_FREEZE_H = 4
+
+
+class PsgldError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class psgld_likelihood(C.Structure):
+    _fields_ = [("beta", C.c_double), ("phi", C.c_double)]
+
+
+class psgld_prior(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lambda_w", C.c_double), ("lambda_h", C.c_double),
+                ("mirror", C.c_int32)]
+
+
+class psgld_eps_schedule(C.Structure):
+    _fields_ = [("a", C.c_double), ("t0", C.c_double), ("gamma", C.c_double)]
+
+
+class psgld_options(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("burn_in", C.c_int64), ("thin", C.c_int32),
+                ("precision", C.c_int32), ("dense_threshold", C.c_double),
+                ("mu_floor", C.c_double), ("row_piece", C.c_void_p), ("col_piece", C.c_void_p),
+                ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32)]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_ST = C.c_int
+
+# name -> (argtypes, restype); the exported symbols of include/psgld.h
+SIGNATURES = {
+    "psgld_default_options": ([C.POINTER(psgld_options)], None),
+    "psgld_create": ([_I64, _I64, C.c_int32, C.c_int32, C.POINTER(psgld_likelihood),
+                      C.POINTER(psgld_prior), C.POINTER(psgld_options), C.POINTER(_P)], _ST),
+    "psgld_load_coo": ([_P, _I64, _P, _P, _P], _ST),
+    "psgld_load_dense": ([_P, _P, _P], _ST),
+    "psgld_load_heldout": ([_P, _I64, _P, _P, _P], _ST),
+    "psgld_set_factors": ([_P, _P, _P], _ST),
+    "psgld_step": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
+    "psgld_sync": ([_P], _ST),
+    "psgld_get_factors": ([_P, _P, _P], _ST),
+    "psgld_posterior_mean": ([_P, _P, _P], _ST),
+    "psgld_posterior_var": ([_P, _P, _P], _ST),
+    "psgld_num_samples": ([_P, C.POINTER(_I64)], _ST),
+    "psgld_heldout_predictions": ([_P, _P], _ST),
+    "psgld_heldout_rmse": ([_P, C.POINTER(C.c_double)], _ST),
+    "psgld_log_likelihood": ([_P, C.POINTER(C.c_double)], _ST),
+    "psgld_iteration": ([_P, C.POINTER(_I64)], _ST),
+    "psgld_part_sizes": ([_P, _P, C.POINTER(_I64)], _ST),
+    "psgld_get_state": ([_P, _P, C.POINTER(C.c_size_t)], _ST),
+    "psgld_set_state": ([_P, _P, C.c_size_t], _ST),
+    "psgld_memory_bytes": ([_P, C.POINTER(_I64)], _ST),
+    "psgld_get_stream": ([_P, C.POINTER(_P)], _ST),
+    "psgld_last_error": ([_P], C.c_char_p),
+    "psgld_destroy": ([_P], None),
+    "psgld_philox_blocks": ([_I64, _P, _P, _P, C.c_int32], _ST),
+    "psgld_normals": ([_I64, C.c_uint64, _P, _P, _P, C.c_int32, _P, _P, C.c_int32], _ST),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libpsgld.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1506_01418_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(status, ctx=None):
+    if status != PSGLD_OK:
+        msg = lib().psgld_last_error(ctx)
+        raise PsgldError(status, msg.decode() if msg else "")
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ------------------------------------------------------------ C-named wrappers
+def psgld_default_options() -> psgld_options:
+    o = psgld_options()
+    lib().psgld_default_options(C.byref(o))
+    return o
+
+
+def psgld_create(I, J, K, B, lik: psgld_likelihood, prior: psgld_prior,
+                 opt: Optional[psgld_options] = None):
+    out = C.c_void_p()
+    st = lib().psgld_create(I, J, K, B, C.byref(lik), C.byref(prior),
+                            C.byref(opt) if opt is not None else None, C.byref(out))
+    _check(st, None)
+    return out
+
+
+def psgld_load_coo(ctx, row, col, val):
+    row, col, val = _arr(row, np.int32), _arr(col, np.int32), _arr(val, np.float32)
+    _check(lib().psgld_load_coo(ctx, len(row), _ptr(row), _ptr(col), _ptr(val)), ctx)
+
+
+def psgld_load_dense(ctx, V, train_mask=None):
+    V = _arr(V, np.float32)
+    m = None if train_mask is None else _arr(train_mask, np.uint8)
+    _check(lib().psgld_load_dense(ctx, _ptr(V), _ptr(m)), ctx)
+
+
+def psgld_load_heldout(ctx, row, col, val=None):
+    row, col = _arr(row, np.int32), _arr(col, np.int32)
+    v = None if val is None else _arr(val, np.float32)
+    _check(lib().psgld_load_heldout(ctx, len(row), _ptr(row), _ptr(col), _ptr(v)), ctx)
+
+
+def psgld_set_factors(ctx, W, H):
+    W, H = _arr(W, np.float32), _arr(H, np.float32)
+    _check(lib().psgld_set_factors(ctx, _ptr(W), _ptr(H)), ctx)
+
+
+def psgld_step(ctx, n_iter, sched: psgld_eps_schedule):
+    _check(lib().psgld_step(ctx, int(n_iter), C.byref(sched)), ctx)
+
+
+def psgld_sync(ctx):
+    _check(lib().psgld_sync(ctx), ctx)
+
+
+def psgld_get_factors(ctx, I, J, K):
+    W = np.zeros((I, K), np.float32)
+    H = np.zeros((K, J), np.float32)
+    _check(lib().psgld_get_factors(ctx, _ptr(W), _ptr(H)), ctx)
+    return W, H
+
+
+def psgld_posterior_mean(ctx, I, J, K):
+    W = np.zeros((I, K))
+    H = np.zeros((K, J))
+    _check(lib().psgld_posterior_mean(ctx, _ptr(W), _ptr(H)), ctx)
+    return W, H
+
+
+def psgld_posterior_var(ctx, I, J, K):
+    W = np.zeros((I, K))
+    H = np.zeros((K, J))
+    _check(lib().psgld_posterior_var(ctx, _ptr(W), _ptr(H)), ctx)
+    return W, H
+
+
+def psgld_num_samples(ctx) -> int:
+    s = C.c_int64()
+    _check(lib().psgld_num_samples(ctx, C.byref(s)), ctx)
+    return s.value
+
+
+def psgld_heldout_predictions(ctx, n):
+    out = np.zeros(n)
+    _check(lib().psgld_heldout_predictions(ctx, _ptr(out)), ctx)
+    return out
+
+
+def psgld_heldout_rmse(ctx) -> float:
+    r = C.c_double()
+    _check(lib().psgld_heldout_rmse(ctx, C.byref(r)), ctx)
+    return r.value
+
+
+def psgld_log_likelihood(ctx) -> float:
+    r = C.c_double()
+    _check(lib().psgld_log_likelihood(ctx, C.byref(r)), ctx)
+    return r.value
+
+
+def psgld_iteration(ctx) -> int:
+    t = C.c_int64()
+    _check(lib().psgld_iteration(ctx, C.byref(t)), ctx)
+    return t.value
+
+
+def psgld_part_sizes(ctx, B):
+    n_p = np.zeros(B, np.int64)
+    N = C.c_int64()
+    _check(lib().psgld_part_sizes(ctx, _ptr(n_p), C.byref(N)), ctx)
+    return n_p, N.value
+
+
+def psgld_get_state(ctx) -> bytes:
+    size = C.c_size_t(0)
+    _check(lib().psgld_get_state(ctx, None, C.byref(size)), ctx)
+    buf = C.create_string_buffer(size.value)
+    _check(lib().psgld_get_state(ctx, buf, C.byref(size)), ctx)
+    return buf.raw
+
+
+def psgld_set_state(ctx, state: bytes):
+    buf = C.create_string_buffer(state, len(state))
+    _check(lib().psgld_set_state(ctx, buf, len(state)), ctx)
+
+
+def psgld_memory_bytes(ctx) -> int:
+    b = C.c_int64()
+    _check(lib().psgld_memory_bytes(ctx, C.byref(b)), ctx)
+    return b.value
+
+
+def psgld_get_stream(ctx) -> int:
+    s = C.c_void_p()
+    _check(lib().psgld_get_stream(ctx, C.byref(s)), ctx)
+    return s.value or 0
+
+
+def psgld_last_error(ctx) -> str:
+    m = lib().psgld_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def psgld_destroy(ctx):
+    lib().psgld_destroy(ctx)
+
+
+def psgld_philox_blocks(ctr, key, device=0):
+    ctr = _arr(ctr, np.uint32).reshape(-1, 4)
+    key = _arr(key, np.uint32).reshape(-1, 2)
+    out = np.zeros_like(ctr)
+    _check(lib().psgld_philox_blocks(len(ctr), _ptr(ctr), _ptr(key), _ptr(out), device))
+    return out
+
+
+def psgld_normals(seed, t, stream, index, K, device=0):
+    t, stream, index = _arr(t, np.int64), _arr(stream, np.uint32), _arr(index, np.int64)
+    n = len(t)
+    z = np.zeros((n, K), np.float32)
+    r = np.zeros((n, K), np.float32)
+    _check(lib().psgld_normals(n, seed, _ptr(t), _ptr(stream), _ptr(index), K, _ptr(z), _ptr(r),
+                               device))
+    return z, r
+
+
+# ------------------------------------------------------------ convenience class
+class PSGLD:
+    """One sampler context.  Arguments mirror psgld_create and psgld_options."""
+
+    def __init__(self, I, J, K, B, beta=2.0, phi=1.0, prior="gaussian", lambda_w=1.0,
+                 lambda_h=1.0, mirror=False, seed=0, burn_in=0, thin=1, precision=PSGLD_FP32,
+                 dense_threshold=0.3, mu_floor=1e-6, row_piece=None, col_piece=None,
+                 stream: Optional[int] = None, test_flags=0, device=0):
+        self.I, self.J, self.K, self.B = int(I), int(J), int(K), int(B)
+        lik = psgld_likelihood(beta, phi)
+        pr = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
+                         lambda_w, lambda_h, int(bool(mirror)))
+        opt = psgld_default_options()
+        opt.seed, opt.burn_in, opt.thin = seed, burn_in, thin
+        opt.precision, opt.dense_threshold, opt.mu_floor = precision, dense_threshold, mu_floor
+        self._pieces = [None if x is None else _arr(x, np.int32) for x in (row_piece, col_piece)]
+        opt.row_piece = _ptr(self._pieces[0])
+        opt.col_piece = _ptr(self._pieces[1])
+        opt.stream = stream or None
+        opt.test_flags, opt.device = test_flags, device
+        self.ctx = psgld_create(self.I, self.J, self.K, self.B, lik, pr, opt)
+        self.n_heldout = 0
+
+    @classmethod
+    def from_workload(cls, wl, **overrides):
+        kw = dict(beta=wl.beta, phi=wl.phi, prior=wl.prior, lambda_w=wl.lambda_w,
+                  lambda_h=wl.lambda_h, mirror=wl.mirror, seed=wl.seed, burn_in=wl.burn_in,
+                  thin=wl.thin)
+        kw.update(overrides)
+        s = cls(wl.I, wl.J, wl.K, wl.B, **kw)
+        s.load_coo(wl.row, wl.col, wl.val)
+        if len(wl.hrow):
+            s.load_heldout(wl.hrow, wl.hcol, wl.hval)
+        s.set_factors(wl.W0, wl.H0)
+        return s
+
+    def load_coo(self, row, col, val):
+        psgld_load_coo(self.ctx, row, col, val)
+
+    def load_dense(self, V, mask=None):
+        psgld_load_dense(self.ctx, V, mask)
+
+    def load_heldout(self, row, col, val=None):
+        psgld_load_heldout(self.ctx, row, col, val)
+        self.n_heldout = len(row)
+
+    def set_factors(self, W, H):
+        psgld_set_factors(self.ctx, W, H)
+
+    def step(self, n_iter, a, t0=1.0, gamma=0.51):
+        psgld_step(self.ctx, n_iter, psgld_eps_schedule(a, t0, gamma))
+
+    def sync(self):
+        psgld_sync(self.ctx)
+
+    def factors(self):
+        return psgld_get_factors(self.ctx, self.I, self.J, self.K)
+
+    def posterior_mean(self):
+        return psgld_posterior_mean(self.ctx, self.I, self.J, self.K)
+
+    def posterior_var(self):
+        return psgld_posterior_var(self.ctx, self.I, self.J, self.K)
+
+    def num_samples(self):
+        return psgld_num_samples(self.ctx)
+
+    def heldout_predictions(self):
+        return psgld_heldout_predictions(self.ctx, self.n_heldout)
+
+    def heldout_rmse(self):
+        return psgld_heldout_rmse(self.ctx)
+
+    def log_likelihood(self):
+        return psgld_log_likelihood(self.ctx)
+
+    def iteration(self):
+        return psgld_iteration(self.ctx)
+
+    def part_sizes(self):
+        return psgld_part_sizes(self.ctx, self.B)
+
+    def get_state(self):
+        return psgld_get_state(self.ctx)
+
+    def set_state(self, state):
+        psgld_set_state(self.ctx, state)
+
+    def memory_bytes(self):
+        return psgld_memory_bytes(self.ctx)
+
+    def stream(self):
+        return psgld_get_stream(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            psgld_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,930 @@
+// Host runtime of libpsgld: the C ABI declared in psgld.h.
+//
+// Layout in device memory (HBM), built once on the host at load time:
+//  * W is I x Kp and H is stored transposed, J x Kp (Kp = K rounded up to a
+//    multiple of 4, padding held at zero), each twice (ping-pong): an
+//    iteration reads one copy and writes the other, so every row and column
+//    update reads only the previous state (Eq. (8)-(9)).
+//  * Training entries are bucketed by part (part of (i,j) = (c - b) mod B
+//    for row piece b and column piece c) and stored twice, part-major:
+//    row-sorted for the W items (partner = column) and column-sorted for the
+//    H items (partner = row).  Offsets are prefix sums over (part, row) and
+//    (part, column), so part p's row offsets are a contiguous slice.
+//  * For every part, rows and columns are listed in decreasing order of
+//    their entry count and packed into work-group tasks (see sparse.hip).
+//  * FP64 running sums of x and x^2, and FP64 held-out predictive sums.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "psgld.h"
+
+using namespace psgld;
+
+namespace {
+
+thread_local std::string g_create_error;
+constexpr int kEntriesPerGroup = 16;   // target entries per group before splitting an item
+constexpr uint32_t kStateMagic = 0x50534744u;  // "PSGD"
+constexpr uint32_t kStateVersion = 1;
+
+bool is_gfx950(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return false;
+    return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+}  // namespace
+
+struct psgld_ctx {
+    int64_t I = 0, J = 0;
+    int32_t K = 0, B = 0, Kp = 0, nq = 0, lpg = 0;
+    psgld_likelihood lik{};
+    psgld_prior prior{};
+    psgld_options opt{};
+    int lik_kind = LIK_GENERAL;
+    std::string err;
+
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool device_ready = false;
+    bool loaded = false, factors_set = false, heldout_loaded = false;
+
+    std::vector<int32_t> row_piece, col_piece;
+    int64_t N = 0;
+    std::vector<int64_t> n_p;
+    std::vector<int64_t> task_off, n_tasks;
+
+    std::vector<void *> allocs;
+    int64_t bytes = 0;
+    float *W[2] = {nullptr, nullptr}, *H[2] = {nullptr, nullptr};
+    int cur = 0;
+    int32_t *rowptr = nullptr, *colptr = nullptr;
+    Entry *ent_r = nullptr, *ent_c = nullptr;
+    int32_t *row_of_entry = nullptr;
+    int32_t *items = nullptr;
+    Task *tasks = nullptr;
+    double *sum[2] = {nullptr, nullptr}, *sum2[2] = {nullptr, nullptr};
+    int64_t n_kept = 0;
+
+    int64_t n_ho = 0;
+    int32_t *ho_ptr = nullptr;
+    HeldEntry *ho_ent = nullptr;
+    double *ho_sum = nullptr;
+    std::vector<float> ho_val;
+    bool ho_has_val = false;
+    std::vector<int32_t> ho_part;
+    std::vector<int64_t> part_visits;
+
+    int32_t *nonfinite = nullptr;
+    double *ll_partials = nullptr, *ll_out = nullptr;
+    int ll_blocks = 0;
+    int64_t t = 0;
+
+    psgld_status fail(psgld_status s, const std::string &msg)
+    {
+        err = msg;
+        return s;
+    }
+};
+
+#define HIPTRY(ctx, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return (ctx)->fail(PSGLD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+template <typename T>
+psgld_status dev_alloc(psgld_ctx *c, T **p, size_t count)
+{
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return c->fail(PSGLD_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->allocs.push_back(q);
+    c->bytes += static_cast<int64_t>(bytes);
+    *p = static_cast<T *>(q);
+    return PSGLD_OK;
+}
+
+psgld_status ensure_device(psgld_ctx *c)
+{
+    if (c->device_ready) return PSGLD_OK;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= c->opt.device) {
+        (void)hipGetLastError();
+        return c->fail(PSGLD_E_DEVICE, "no HIP device " + std::to_string(c->opt.device));
+    }
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    if (!is_gfx950(c->opt.device)) return c->fail(PSGLD_E_DEVICE, "device is not gfx950 (MI355X)");
+    if (c->opt.stream) {
+        c->stream = static_cast<hipStream_t>(c->opt.stream);
+    } else {
+        HIPTRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    psgld_status s = dev_alloc(c, &c->nonfinite, 1);
+    if (s) return s;
+    const int32_t big = INT_MAX;
+    HIPTRY(c, hipMemcpy(c->nonfinite, &big, sizeof(big), hipMemcpyHostToDevice));
+    c->device_ready = true;
+    return PSGLD_OK;
+}
+
+template <typename T>
+psgld_status upload(psgld_ctx *c, T **dst, const std::vector<T> &src)
+{
+    psgld_status s = dev_alloc(c, dst, src.size());
+    if (s) return s;
+    if (!src.empty())
+        HIPTRY(c, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PSGLD_OK;
+}
+
+int32_t part_of(const psgld_ctx *c, int32_t i, int32_t j)
+{
+    return (c->col_piece[j] - c->row_piece[i] + c->B) % c->B;
+}
+
+int next_pow2(int64_t v)
+{
+    int p = 1;
+    while (p < v) p *= 2;
+    return p;
+}
+
+// Splits one side's size-sorted item list of one part into tasks.
+void build_tasks(const std::vector<int64_t> &cnt_sorted, int32_t side, int32_t first_off,
+                 int Q, std::vector<Task> &out)
+{
+    const int64_t n = static_cast<int64_t>(cnt_sorted.size());
+    int64_t pos = 0;
+    while (pos < n) {
+        const int64_t need = (cnt_sorted[pos] + kEntriesPerGroup - 1) / kEntriesPerGroup;
+        const int G = std::min(Q, next_pow2(std::max<int64_t>(need, 1)));
+        const int per = Q / G;
+        int64_t end = pos;
+        while (end < n && end - pos < per) {
+            const int64_t nd = (cnt_sorted[end] + kEntriesPerGroup - 1) / kEntriesPerGroup;
+            if (std::min(Q, next_pow2(std::max<int64_t>(nd, 1))) != G) break;
+            ++end;
+        }
+        out.push_back(Task{side, first_off + static_cast<int32_t>(pos),
+                           static_cast<int32_t>(end - pos), G});
+        pos = end;
+    }
+}
+
+// Builds and uploads the part-major layout from training coordinates.
+psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const int32_t *col,
+                          const float *val)
+{
+    const int64_t I = c->I, J = c->J;
+    const int32_t B = c->B;
+    // bucket by (part, row) and by (part, column): counting sort
+    std::vector<int32_t> part(nnz);
+    for (int64_t e = 0; e < nnz; ++e) part[e] = part_of(c, row[e], col[e]);
+    std::vector<int32_t> pre_r(static_cast<size_t>(B) * I + 1, 0), pre_c(static_cast<size_t>(B) * J + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) {
+        pre_r[static_cast<size_t>(part[e]) * I + row[e] + 1]++;
+        pre_c[static_cast<size_t>(part[e]) * J + col[e] + 1]++;
+    }
+    for (size_t k = 1; k < pre_r.size(); ++k) pre_r[k] += pre_r[k - 1];
+    for (size_t k = 1; k < pre_c.size(); ++k) pre_c[k] += pre_c[k - 1];
+    std::vector<Entry> er(nnz), ec(nnz);
+    std::vector<int32_t> rows_of(nnz);
+    {
+        std::vector<int32_t> fr(pre_r.begin(), pre_r.end() - 1), fc(pre_c.begin(), pre_c.end() - 1);
+        for (int64_t e = 0; e < nnz; ++e) {
+            const int32_t kr = fr[static_cast<size_t>(part[e]) * I + row[e]]++;
+            er[kr] = Entry{col[e], val[e]};
+            rows_of[kr] = row[e];
+            const int32_t kc = fc[static_cast<size_t>(part[e]) * J + col[e]]++;
+            ec[kc] = Entry{row[e], val[e]};
+        }
+    }
+    auto by_idx = [](const Entry &a, const Entry &b) { return a.idx < b.idx; };
+    for (size_t k = 0; k + 1 < pre_r.size(); ++k) {
+        if (pre_r[k + 1] - pre_r[k] > 1) {
+            std::sort(er.begin() + pre_r[k], er.begin() + pre_r[k + 1], by_idx);
+            for (int32_t m = pre_r[k] + 1; m < pre_r[k + 1]; ++m)
+                if (er[m].idx == er[m - 1].idx) {
+                    const int64_t i = static_cast<int64_t>(k % I);
+                    return c->fail(PSGLD_E_ARG, "duplicate training entry (" + std::to_string(i) +
+                                                    ", " + std::to_string(er[m].idx) + ")");
+                }
+        }
+    }
+    for (size_t k = 0; k + 1 < pre_c.size(); ++k)
+        if (pre_c[k + 1] - pre_c[k] > 1) std::sort(ec.begin() + pre_c[k], ec.begin() + pre_c[k + 1], by_idx);
+
+    c->N = nnz;
+    c->n_p.assign(B, 0);
+    for (int32_t p = 0; p < B; ++p) c->n_p[p] = pre_r[static_cast<size_t>(p + 1) * I] - pre_r[static_cast<size_t>(p) * I];
+
+    // items sorted by decreasing entry count (ties by index) and their tasks
+    const int Q = sparse_block_threads() / c->lpg;
+    std::vector<int32_t> items(static_cast<size_t>(B) * (I + J));
+    std::vector<Task> tasks;
+    c->task_off.assign(B, 0);
+    c->n_tasks.assign(B, 0);
+    for (int32_t p = 0; p < B; ++p) {
+        int32_t *it = items.data() + static_cast<size_t>(p) * (I + J);
+        std::vector<Task> tp;
+        for (int side = 0; side < 2; ++side) {
+            const int64_t n = side == 0 ? I : J;
+            const int32_t *pre = side == 0 ? pre_r.data() + static_cast<size_t>(p) * I
+                                           : pre_c.data() + static_cast<size_t>(p) * J;
+            int32_t *lst = it + (side == 0 ? 0 : I);
+            std::iota(lst, lst + n, 0);
+            std::stable_sort(lst, lst + n, [pre](int32_t a, int32_t b) {
+                return pre[a + 1] - pre[a] > pre[b + 1] - pre[b];
+            });
+            std::vector<int64_t> cnt(n);
+            for (int64_t m = 0; m < n; ++m) cnt[m] = pre[lst[m] + 1] - pre[lst[m]];
+            build_tasks(cnt, side, side == 0 ? 0 : static_cast<int32_t>(I), Q, tp);
+        }
+        std::stable_sort(tp.begin(), tp.end(), [](const Task &a, const Task &b) { return a.G > b.G; });
+        c->task_off[p] = static_cast<int64_t>(tasks.size());
+        c->n_tasks[p] = static_cast<int64_t>(tp.size());
+        tasks.insert(tasks.end(), tp.begin(), tp.end());
+    }
+
+    psgld_status s;
+    if ((s = upload(c, &c->rowptr, pre_r))) return s;
+    if ((s = upload(c, &c->colptr, pre_c))) return s;
+    if ((s = upload(c, &c->ent_r, er))) return s;
+    if ((s = upload(c, &c->ent_c, ec))) return s;
+    if ((s = upload(c, &c->row_of_entry, rows_of))) return s;
+    if ((s = upload(c, &c->items, items))) return s;
+    if ((s = upload(c, &c->tasks, tasks))) return s;
+
+    const size_t nw = static_cast<size_t>(I) * c->Kp, nh = static_cast<size_t>(J) * c->Kp;
+    for (int b = 0; b < 2; ++b) {
+        if ((s = dev_alloc(c, &c->W[b], nw))) return s;
+        if ((s = dev_alloc(c, &c->H[b], nh))) return s;
+        HIPTRY(c, hipMemset(c->W[b], 0, nw * sizeof(float)));
+        HIPTRY(c, hipMemset(c->H[b], 0, nh * sizeof(float)));
+    }
+    for (int side = 0; side < 2; ++side) {
+        const size_t n = side == 0 ? nw : nh;
+        if ((s = dev_alloc(c, &c->sum[side], n))) return s;
+        if ((s = dev_alloc(c, &c->sum2[side], n))) return s;
+        HIPTRY(c, hipMemset(c->sum[side], 0, n * sizeof(double)));
+        HIPTRY(c, hipMemset(c->sum2[side], 0, n * sizeof(double)));
+    }
+    c->ll_blocks = 1024;
+    if ((s = dev_alloc(c, &c->ll_partials, c->ll_blocks))) return s;
+    if ((s = dev_alloc(c, &c->ll_out, 1))) return s;
+    c->part_visits.assign(B, 0);
+    c->loaded = true;
+    return PSGLD_OK;
+}
+
+psgld_status check_values(psgld_ctx *c, int64_t n, const float *val)
+{
+    for (int64_t e = 0; e < n; ++e) {
+        const float v = val[e];
+        if (!std::isfinite(v)) return c->fail(PSGLD_E_ARG, "non-finite value at entry " + std::to_string(e));
+        if (c->lik.beta <= 1.0 && v < 0.f)
+            return c->fail(PSGLD_E_ARG, "negative value at entry " + std::to_string(e) + " with beta <= 1");
+        if (c->lik.beta <= 0.0 && v <= 0.f)
+            return c->fail(PSGLD_E_ARG, "non-positive value at entry " + std::to_string(e) + " with beta <= 0");
+    }
+    return PSGLD_OK;
+}
+
+psgld_status check_coords(psgld_ctx *c, int64_t n, const int32_t *row, const int32_t *col)
+{
+    for (int64_t e = 0; e < n; ++e) {
+        if (row[e] < 0 || row[e] >= c->I || col[e] < 0 || col[e] >= c->J)
+            return c->fail(PSGLD_E_ARG, "coordinate out of range at entry " + std::to_string(e));
+    }
+    return PSGLD_OK;
+}
+
+psgld_status sync_and_check(psgld_ctx *c)
+{
+    if (!c->device_ready) return PSGLD_OK;
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    int32_t flag = INT_MAX;
+    HIPTRY(c, hipMemcpy(&flag, c->nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag != INT_MAX)
+        return c->fail(PSGLD_E_NUMERIC, "non-finite value in W or H at iteration " + std::to_string(flag));
+    return PSGLD_OK;
+}
+
+// Device FP32 factor (rows x Kp) -> host rows x K, optionally transposed to K x rows.
+template <typename TOut, typename TDev>
+psgld_status fetch_factor(psgld_ctx *c, const TDev *dev, int64_t rows, bool transpose, TOut *out,
+                          double scale)
+{
+    std::vector<TDev> tmp(static_cast<size_t>(rows) * c->Kp);
+    HIPTRY(c, hipMemcpy(tmp.data(), dev, tmp.size() * sizeof(TDev), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < rows; ++r)
+        for (int32_t k = 0; k < c->K; ++k) {
+            const TOut v = static_cast<TOut>(static_cast<double>(tmp[static_cast<size_t>(r) * c->Kp + k]) * scale);
+            if (transpose) out[static_cast<size_t>(k) * rows + r] = v;
+            else out[static_cast<size_t>(r) * c->K + k] = v;
+        }
+    return PSGLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void psgld_default_options(psgld_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->seed = 0;
+    opt->burn_in = 0;
+    opt->thin = 1;
+    opt->precision = PSGLD_FP32;
+    opt->dense_threshold = 0.3;
+    opt->mu_floor = 1e-6;
+    opt->row_piece = nullptr;
+    opt->col_piece = nullptr;
+    opt->stream = nullptr;
+    opt->test_flags = 0;
+    opt->device = 0;
+}
+
+psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgld_likelihood *lik,
+                          const psgld_prior *prior, const psgld_options *opt, psgld_ctx **out)
+{
+    auto bad = [](const std::string &m) {
+        g_create_error = m;
+        return PSGLD_E_ARG;
+    };
+    if (!out) return bad("out is NULL");
+    *out = nullptr;
+    if (!lik || !prior) return bad("likelihood and prior are required");
+    if (I < 1 || J < 1 || I > INT32_MAX || J > INT32_MAX) return bad("I and J must be in [1, 2^31)");
+    if (K < 1 || K > 256) return bad("K must be in [1, 256]");
+    if (B < 1 || B > I || B > J) return bad("B must be in [1, min(I, J)]");
+    if (!(lik->phi > 0.0) || !std::isfinite(lik->phi) || !std::isfinite(lik->beta)) return bad("phi must be > 0, beta finite");
+    if (lik->beta > 1.0 && lik->beta < 2.0) return bad("no Tweedie model exists for 1 < beta < 2");
+    if (prior->kind != PSGLD_PRIOR_EXPONENTIAL && prior->kind != PSGLD_PRIOR_GAUSSIAN) return bad("unknown prior kind");
+    if (!(prior->lambda_w > 0.0) || !(prior->lambda_h > 0.0)) return bad("prior rates must be > 0");
+    psgld_options o;
+    psgld_default_options(&o);
+    if (opt) o = *opt;
+    if (o.thin < 1) return bad("thin must be >= 1");
+    if (o.burn_in < 0) return bad("burn_in must be >= 0");
+    if (!(o.mu_floor > 0.0)) return bad("mu_floor must be > 0");
+    if (o.precision != PSGLD_FP32 && o.precision != PSGLD_BF16_DENSE) return bad("unknown precision");
+    if (o.device < 0) return bad("device must be >= 0");
+
+    psgld_ctx *c = new (std::nothrow) psgld_ctx();
+    if (!c) {
+        g_create_error = "out of host memory";
+        return PSGLD_E_NOMEM;
+    }
+    c->I = I;
+    c->J = J;
+    c->K = K;
+    c->B = B;
+    c->Kp = (K + 3) / 4 * 4;
+    c->nq = (K + 3) / 4;
+    c->lpg = sparse_threads_per_group(K);
+    c->lik = *lik;
+    c->prior = *prior;
+    c->opt = o;
+    c->lik_kind = lik->beta == 2.0 ? LIK_GAUSS : (lik->beta == 1.0 ? LIK_POISSON : LIK_GENERAL);
+    // partitions P_B([I]), P_B([J]): given, or contiguous with the first (n mod B) pieces longer
+    for (int side = 0; side < 2; ++side) {
+        const int64_t n = side == 0 ? I : J;
+        const int32_t *given = side == 0 ? o.row_piece : o.col_piece;
+        std::vector<int32_t> &pc = side == 0 ? c->row_piece : c->col_piece;
+        pc.resize(n);
+        if (given) {
+            std::vector<int64_t> cnt(B, 0);
+            for (int64_t m = 0; m < n; ++m) {
+                if (given[m] < 0 || given[m] >= B) {
+                    delete c;
+                    return bad("piece index out of range");
+                }
+                pc[m] = given[m];
+                cnt[given[m]]++;
+            }
+            for (int32_t b = 0; b < B; ++b)
+                if (cnt[b] == 0) {
+                    delete c;
+                    return bad("every piece of a partition must be non-empty");
+                }
+        } else {
+            const int64_t base = n / B, extra = n % B;
+            int64_t pos = 0;
+            for (int32_t b = 0; b < B; ++b)
+                for (int64_t m = 0; m < base + (b < extra ? 1 : 0); ++m) pc[pos++] = b;
+        }
+    }
+    c->opt.row_piece = nullptr;
+    c->opt.col_piece = nullptr;
+    *out = c;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_load_coo(psgld_ctx *c, int64_t nnz, const int32_t *row, const int32_t *col,
+                            const float *val)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (c->loaded) return c->fail(PSGLD_E_STATE, "data already loaded");
+    if (nnz < 0 || nnz >= INT32_MAX) return c->fail(PSGLD_E_ARG, "nnz must be in [0, 2^31)");
+    if (nnz > 0 && (!row || !col || !val)) return c->fail(PSGLD_E_ARG, "row, col and val are required");
+    psgld_status s;
+    if ((s = check_coords(c, nnz, row, col))) return s;
+    if ((s = check_values(c, nnz, val))) return s;
+    if ((s = ensure_device(c))) return s;
+    return build_layout(c, nnz, row, col, val);
+}
+
+psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (c->loaded) return c->fail(PSGLD_E_STATE, "data already loaded");
+    if (!V) return c->fail(PSGLD_E_ARG, "V is required");
+    std::vector<int32_t> row, col;
+    std::vector<float> val;
+    for (int64_t i = 0; i < c->I; ++i)
+        for (int64_t j = 0; j < c->J; ++j) {
+            const size_t m = static_cast<size_t>(i) * c->J + j;
+            if (mask && !mask[m]) continue;
+            row.push_back(static_cast<int32_t>(i));
+            col.push_back(static_cast<int32_t>(j));
+            val.push_back(V[m]);
+        }
+    return psgld_load_coo(c, static_cast<int64_t>(row.size()), row.data(), col.data(), val.data());
+}
+
+psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
+                                const float *val)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load training data first");
+    if (c->heldout_loaded) return c->fail(PSGLD_E_STATE, "held-out cells already loaded");
+    if (c->t > 0) return c->fail(PSGLD_E_STATE, "held-out cells must be loaded before the first step");
+    if (n < 0 || n >= INT32_MAX) return c->fail(PSGLD_E_ARG, "n must be in [0, 2^31)");
+    if (n > 0 && (!row || !col)) return c->fail(PSGLD_E_ARG, "row and col are required");
+    psgld_status s;
+    if ((s = check_coords(c, n, row, col))) return s;
+    if (val)
+        for (int64_t e = 0; e < n; ++e)
+            if (!std::isfinite(val[e])) return c->fail(PSGLD_E_ARG, "non-finite held-out value");
+    const int64_t I = c->I;
+    const int32_t B = c->B;
+    std::vector<int32_t> pre(static_cast<size_t>(B) * I + 1, 0);
+    c->ho_part.resize(n);
+    for (int64_t e = 0; e < n; ++e) {
+        c->ho_part[e] = part_of(c, row[e], col[e]);
+        pre[static_cast<size_t>(c->ho_part[e]) * I + row[e] + 1]++;
+    }
+    for (size_t k = 1; k < pre.size(); ++k) pre[k] += pre[k - 1];
+    std::vector<HeldEntry> he(n);
+    {
+        std::vector<int32_t> fill(pre.begin(), pre.end() - 1);
+        for (int64_t e = 0; e < n; ++e)
+            he[fill[static_cast<size_t>(c->ho_part[e]) * I + row[e]]++] = HeldEntry{col[e], static_cast<int32_t>(e)};
+    }
+    // distinct cells, disjoint from the training entries
+    std::vector<int32_t> rp(static_cast<size_t>(B) * I + 1);
+    HIPTRY(c, hipMemcpy(rp.data(), c->rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<Entry> er(static_cast<size_t>(c->N));
+    if (c->N) HIPTRY(c, hipMemcpy(er.data(), c->ent_r, er.size() * sizeof(Entry), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k + 1 < pre.size(); ++k) {
+        std::sort(he.begin() + pre[k], he.begin() + pre[k + 1],
+                  [](const HeldEntry &a, const HeldEntry &b) { return a.col < b.col; });
+        for (int32_t m = pre[k]; m < pre[k + 1]; ++m) {
+            if (m > pre[k] && he[m].col == he[m - 1].col) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
+            const Entry *b0 = er.data() + rp[k], *b1 = er.data() + rp[k + 1];
+            const Entry *f = std::lower_bound(b0, b1, he[m].col, [](const Entry &a, int32_t v) { return a.idx < v; });
+            if (f != b1 && f->idx == he[m].col)
+                return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
+        }
+    }
+    if ((s = upload(c, &c->ho_ptr, pre))) return s;
+    if ((s = upload(c, &c->ho_ent, he))) return s;
+    if ((s = dev_alloc(c, &c->ho_sum, static_cast<size_t>(n)))) return s;
+    HIPTRY(c, hipMemset(c->ho_sum, 0, std::max<int64_t>(n, 1) * sizeof(double)));
+    c->n_ho = n;
+    c->ho_has_val = val != nullptr;
+    c->ho_val.assign(val ? val : nullptr, val ? val + n : nullptr);
+    c->heldout_loaded = true;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_set_factors(psgld_ctx *c, const float *W, const float *H)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load data first");
+    if (!W || !H) return c->fail(PSGLD_E_ARG, "W and H are required");
+    const int64_t I = c->I, J = c->J;
+    const int32_t K = c->K, Kp = c->Kp;
+    std::vector<float> w(static_cast<size_t>(I) * Kp, 0.f), h(static_cast<size_t>(J) * Kp, 0.f);
+    for (int64_t i = 0; i < I; ++i)
+        for (int32_t k = 0; k < K; ++k) {
+            float v = W[static_cast<size_t>(i) * K + k];
+            if (!std::isfinite(v)) return c->fail(PSGLD_E_ARG, "non-finite W");
+            w[static_cast<size_t>(i) * Kp + k] = c->prior.mirror ? std::fabs(v) : v;
+        }
+    for (int32_t k = 0; k < K; ++k)
+        for (int64_t j = 0; j < J; ++j) {
+            float v = H[static_cast<size_t>(k) * J + j];
+            if (!std::isfinite(v)) return c->fail(PSGLD_E_ARG, "non-finite H");
+            h[static_cast<size_t>(j) * Kp + k] = c->prior.mirror ? std::fabs(v) : v;
+        }
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    HIPTRY(c, hipMemcpy(c->W[c->cur], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPTRY(c, hipMemcpy(c->H[c->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->factors_set = true;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *sched)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!sched) return c->fail(PSGLD_E_ARG, "schedule is required");
+    if (n_iter < 0) return c->fail(PSGLD_E_ARG, "n_iter must be >= 0");
+    if (!(sched->a > 0.0) || !std::isfinite(sched->a)) return c->fail(PSGLD_E_ARG, "eps: a must be > 0");
+    if (!(sched->gamma == 0.0 || (sched->gamma > 0.5 && sched->gamma <= 1.0)))
+        return c->fail(PSGLD_E_ARG, "eps: gamma must be in (0.5, 1] (Eq. (4)) or 0");
+    if (sched->gamma > 0.0 && !(sched->t0 > 0.0)) return c->fail(PSGLD_E_ARG, "eps: t0 must be > 0");
+    if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+    if (c->t + n_iter >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    const int64_t I = c->I, J = c->J;
+    for (int64_t it = 0; it < n_iter; ++it) {
+        const int64_t t = c->t;
+        const int32_t p = static_cast<int32_t>(t % c->B);
+        const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(t), -sched->gamma);
+        SparseIterArgs a{};
+        a.x_old[0] = c->W[c->cur];
+        a.x_old[1] = c->H[c->cur];
+        a.x_new[0] = c->W[c->cur ^ 1];
+        a.x_new[1] = c->H[c->cur ^ 1];
+        a.ptr[0] = c->rowptr + static_cast<size_t>(p) * I;
+        a.ptr[1] = c->colptr + static_cast<size_t>(p) * J;
+        a.ent[0] = c->ent_r;
+        a.ent[1] = c->ent_c;
+        a.items = c->items + static_cast<size_t>(p) * (I + J);
+        a.tasks = c->tasks + c->task_off[p];
+        a.n_tasks = static_cast<int32_t>(c->n_tasks[p]);
+        a.K = c->K;
+        a.Kp = c->Kp;
+        a.nq = c->nq;
+        a.eps = static_cast<float>(eps);
+        a.sigma = static_cast<float>(std::sqrt(2.0 * eps));
+        a.scale = c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
+        a.lambda[0] = static_cast<float>(c->prior.lambda_w);
+        a.lambda[1] = static_cast<float>(c->prior.lambda_h);
+        a.inv_phi = static_cast<float>(1.0 / c->lik.phi);
+        a.beta = static_cast<float>(c->lik.beta);
+        a.mu_floor = static_cast<float>(c->opt.mu_floor);
+        a.seed_lo = static_cast<uint32_t>(c->opt.seed);
+        a.seed_hi = static_cast<uint32_t>(c->opt.seed >> 32);
+        a.t = static_cast<uint32_t>(t);
+        a.mirror = c->prior.mirror ? 1 : 0;
+        a.prior_kind = c->prior.kind;
+        a.flags = c->opt.test_flags;
+        const bool post = t >= c->opt.burn_in;
+        a.do_moments = post && (t - c->opt.burn_in) % c->opt.thin == 0;
+        for (int side = 0; side < 2; ++side) {
+            a.sum[side] = c->sum[side];
+            a.sum2[side] = c->sum2[side];
+        }
+        a.do_heldout = post && c->n_ho > 0;
+        a.ho_ptr = c->ho_ptr ? c->ho_ptr + static_cast<size_t>(p) * I : nullptr;
+        a.ho_ent = c->ho_ent;
+        a.ho_sum = c->ho_sum;
+        a.nonfinite = c->nonfinite;
+        HIPTRY(c, launch_sparse_iter(a, c->lik_kind, c->lpg, c->stream));
+        if (a.do_moments) c->n_kept++;
+        if (a.do_heldout) c->part_visits[p]++;
+        c->cur ^= 1;
+        c->t = t + 1;
+    }
+    return PSGLD_OK;
+}
+
+psgld_status psgld_sync(psgld_ctx *c)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    return sync_and_check(c);
+}
+
+psgld_status psgld_get_factors(psgld_ctx *c, float *W, float *H)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->factors_set) return c->fail(PSGLD_E_STATE, "factors not set");
+    if (!W || !H) return c->fail(PSGLD_E_ARG, "W and H are required");
+    psgld_status s = sync_and_check(c);
+    if (s && s != PSGLD_E_NUMERIC) return s;
+    psgld_status s2;
+    if ((s2 = fetch_factor(c, c->W[c->cur], c->I, false, W, 1.0))) return s2;
+    if ((s2 = fetch_factor(c, c->H[c->cur], c->J, true, H, 1.0))) return s2;
+    return s;
+}
+
+psgld_status psgld_num_samples(psgld_ctx *c, int64_t *S)
+{
+    if (!c || !S) return PSGLD_E_ARG;
+    *S = c->n_kept;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_posterior_mean(psgld_ctx *c, double *W, double *H)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!W || !H) return c->fail(PSGLD_E_ARG, "W and H are required");
+    if (c->n_kept == 0) return c->fail(PSGLD_E_STATE, "no samples kept yet");
+    psgld_status s = sync_and_check(c);
+    if (s) return s;
+    const double inv = 1.0 / static_cast<double>(c->n_kept);
+    if ((s = fetch_factor(c, c->sum[0], c->I, false, W, inv))) return s;
+    return fetch_factor(c, c->sum[1], c->J, true, H, inv);
+}
+
+psgld_status psgld_posterior_var(psgld_ctx *c, double *W, double *H)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!W || !H) return c->fail(PSGLD_E_ARG, "W and H are required");
+    if (c->n_kept == 0) return c->fail(PSGLD_E_STATE, "no samples kept yet");
+    psgld_status s = sync_and_check(c);
+    if (s) return s;
+    const double inv = 1.0 / static_cast<double>(c->n_kept);
+    const size_t nw = static_cast<size_t>(c->I) * c->K, nh = static_cast<size_t>(c->J) * c->K;
+    std::vector<double> mw(nw), mh(nh);
+    if ((s = fetch_factor(c, c->sum[0], c->I, false, mw.data(), inv))) return s;
+    if ((s = fetch_factor(c, c->sum[1], c->J, true, mh.data(), inv))) return s;
+    if ((s = fetch_factor(c, c->sum2[0], c->I, false, W, inv))) return s;
+    if ((s = fetch_factor(c, c->sum2[1], c->J, true, H, inv))) return s;
+    for (size_t m = 0; m < nw; ++m) W[m] -= mw[m] * mw[m];
+    for (size_t m = 0; m < nh; ++m) H[m] -= mh[m] * mh[m];
+    return PSGLD_OK;
+}
+
+psgld_status psgld_heldout_predictions(psgld_ctx *c, double *pred)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->heldout_loaded) return c->fail(PSGLD_E_STATE, "no held-out cells loaded");
+    if (!pred && c->n_ho > 0) return c->fail(PSGLD_E_ARG, "pred is required");
+    psgld_status s = sync_and_check(c);
+    if (s) return s;
+    std::vector<double> sums(static_cast<size_t>(c->n_ho));
+    if (c->n_ho) HIPTRY(c, hipMemcpy(sums.data(), c->ho_sum, sums.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < c->n_ho; ++e) {
+        const int64_t v = c->part_visits[c->ho_part[e]];
+        pred[e] = v > 0 ? sums[e] / static_cast<double>(v) : NAN;
+    }
+    return PSGLD_OK;
+}
+
+psgld_status psgld_heldout_rmse(psgld_ctx *c, double *rmse)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!rmse) return c->fail(PSGLD_E_ARG, "rmse is required");
+    if (!c->heldout_loaded || !c->ho_has_val) return c->fail(PSGLD_E_STATE, "no held-out values loaded");
+    std::vector<double> pred(static_cast<size_t>(c->n_ho));
+    psgld_status s = psgld_heldout_predictions(c, pred.data());
+    if (s) return s;
+    double acc = 0.0;
+    int64_t n = 0;
+    for (int64_t e = 0; e < c->n_ho; ++e) {
+        if (std::isnan(pred[e])) continue;
+        const double d = static_cast<double>(c->ho_val[e]) - pred[e];
+        acc += d * d;
+        ++n;
+    }
+    if (n == 0) return c->fail(PSGLD_E_STATE, "no held-out cell visited after burn-in yet");
+    *rmse = std::sqrt(acc / static_cast<double>(n));
+    return PSGLD_OK;
+}
+
+psgld_status psgld_log_likelihood(psgld_ctx *c, double *ll)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!ll) return c->fail(PSGLD_E_ARG, "ll is required");
+    if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, launch_loglik(c->W[c->cur], c->H[c->cur], c->row_of_entry, c->ent_r, c->N, c->K, c->Kp,
+                            c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials, c->ll_blocks,
+                            c->ll_out, c->stream));
+    psgld_status s = sync_and_check(c);
+    if (s) return s;
+    HIPTRY(c, hipMemcpy(ll, c->ll_out, sizeof(double), hipMemcpyDeviceToHost));
+    return PSGLD_OK;
+}
+
+psgld_status psgld_iteration(psgld_ctx *c, int64_t *t)
+{
+    if (!c || !t) return PSGLD_E_ARG;
+    *t = c->t;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_part_sizes(psgld_ctx *c, int64_t *n_p, int64_t *N)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load data first");
+    if (n_p)
+        for (int32_t p = 0; p < c->B; ++p) n_p[p] = c->n_p[p];
+    if (N) *N = c->N;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_get_state(psgld_ctx *c, void *buf, size_t *size)
+{
+    if (!c || !size) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+    const size_t nw = static_cast<size_t>(c->I) * c->Kp, nh = static_cast<size_t>(c->J) * c->Kp;
+    const size_t need = 8 * sizeof(int64_t) + (nw + nh) * sizeof(float) + 2 * (nw + nh) * sizeof(double) +
+                        static_cast<size_t>(c->n_ho) * sizeof(double) + static_cast<size_t>(c->B) * sizeof(int64_t);
+    if (!buf) {
+        *size = need;
+        return PSGLD_OK;
+    }
+    if (*size < need) return c->fail(PSGLD_E_ARG, "state buffer too small");
+    psgld_status s = sync_and_check(c);
+    if (s) return s;
+    char *p = static_cast<char *>(buf);
+    const int64_t hdr[8] = {kStateMagic, kStateVersion, c->I, c->J, c->K, c->B, c->t, c->n_kept};
+    std::memcpy(p, hdr, sizeof(hdr));
+    p += sizeof(hdr);
+    HIPTRY(c, hipMemcpy(p, c->W[c->cur], nw * sizeof(float), hipMemcpyDeviceToHost));
+    p += nw * sizeof(float);
+    HIPTRY(c, hipMemcpy(p, c->H[c->cur], nh * sizeof(float), hipMemcpyDeviceToHost));
+    p += nh * sizeof(float);
+    for (int side = 0; side < 2; ++side) {
+        const size_t n = side == 0 ? nw : nh;
+        HIPTRY(c, hipMemcpy(p, c->sum[side], n * sizeof(double), hipMemcpyDeviceToHost));
+        p += n * sizeof(double);
+        HIPTRY(c, hipMemcpy(p, c->sum2[side], n * sizeof(double), hipMemcpyDeviceToHost));
+        p += n * sizeof(double);
+    }
+    if (c->n_ho) HIPTRY(c, hipMemcpy(p, c->ho_sum, c->n_ho * sizeof(double), hipMemcpyDeviceToHost));
+    p += static_cast<size_t>(c->n_ho) * sizeof(double);
+    std::memcpy(p, c->part_visits.data(), static_cast<size_t>(c->B) * sizeof(int64_t));
+    *size = need;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_set_state(psgld_ctx *c, const void *buf, size_t size)
+{
+    if (!c || !buf) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load data first");
+    const size_t nw = static_cast<size_t>(c->I) * c->Kp, nh = static_cast<size_t>(c->J) * c->Kp;
+    const size_t need = 8 * sizeof(int64_t) + (nw + nh) * sizeof(float) + 2 * (nw + nh) * sizeof(double) +
+                        static_cast<size_t>(c->n_ho) * sizeof(double) + static_cast<size_t>(c->B) * sizeof(int64_t);
+    if (size != need) return c->fail(PSGLD_E_ARG, "state size does not match this context");
+    const char *p = static_cast<const char *>(buf);
+    int64_t hdr[8];
+    std::memcpy(hdr, p, sizeof(hdr));
+    p += sizeof(hdr);
+    if (hdr[0] != kStateMagic || hdr[1] != kStateVersion || hdr[2] != c->I || hdr[3] != c->J ||
+        hdr[4] != c->K || hdr[5] != c->B)
+        return c->fail(PSGLD_E_ARG, "state was saved from a different problem");
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    HIPTRY(c, hipMemcpy(c->W[c->cur], p, nw * sizeof(float), hipMemcpyHostToDevice));
+    p += nw * sizeof(float);
+    HIPTRY(c, hipMemcpy(c->H[c->cur], p, nh * sizeof(float), hipMemcpyHostToDevice));
+    p += nh * sizeof(float);
+    for (int side = 0; side < 2; ++side) {
+        const size_t n = side == 0 ? nw : nh;
+        HIPTRY(c, hipMemcpy(c->sum[side], p, n * sizeof(double), hipMemcpyHostToDevice));
+        p += n * sizeof(double);
+        HIPTRY(c, hipMemcpy(c->sum2[side], p, n * sizeof(double), hipMemcpyHostToDevice));
+        p += n * sizeof(double);
+    }
+    if (c->n_ho) HIPTRY(c, hipMemcpy(c->ho_sum, p, c->n_ho * sizeof(double), hipMemcpyHostToDevice));
+    p += static_cast<size_t>(c->n_ho) * sizeof(double);
+    std::memcpy(c->part_visits.data(), p, static_cast<size_t>(c->B) * sizeof(int64_t));
+    c->t = hdr[6];
+    c->n_kept = hdr[7];
+    c->factors_set = true;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_memory_bytes(psgld_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return PSGLD_E_ARG;
+    *bytes = c->bytes;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_get_stream(psgld_ctx *c, void **stream)
+{
+    if (!c || !stream) return PSGLD_E_ARG;
+    c->err.clear();
+    psgld_status s = ensure_device(c);
+    if (s) return s;
+    *stream = c->stream;
+    return PSGLD_OK;
+}
+
+const char *psgld_last_error(const psgld_ctx *c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+void psgld_destroy(psgld_ctx *c)
+{
+    if (!c) return;
+    if (c->device_ready) {
+        (void)hipSetDevice(c->opt.device);
+        (void)hipStreamSynchronize(c->stream);
+        for (void *p : c->allocs) (void)hipFree(p);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+psgld_status psgld_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
+                                 int32_t device)
+{
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return PSGLD_E_ARG;
+    if (n == 0) return PSGLD_OK;
+    if (hipSetDevice(device) != hipSuccess || !is_gfx950(device)) return PSGLD_E_DEVICE;
+    uint32_t *dc = nullptr, *dk = nullptr, *dout = nullptr;
+    psgld_status s = PSGLD_OK;
+    if (hipMalloc(&dc, n * 16) != hipSuccess || hipMalloc(&dk, n * 8) != hipSuccess ||
+        hipMalloc(&dout, n * 16) != hipSuccess) {
+        s = PSGLD_E_NOMEM;
+    } else if (hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(dk, key, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+               launch_philox_blocks(n, dc, dk, dout, nullptr) != hipSuccess ||
+               hipMemcpy(out, dout, n * 16, hipMemcpyDeviceToHost) != hipSuccess) {
+        s = PSGLD_E_DEVICE;
+    }
+    (void)hipFree(dc);
+    (void)hipFree(dk);
+    (void)hipFree(dout);
+    return s;
+}
+
+psgld_status psgld_normals(int64_t n, uint64_t seed, const int64_t *t, const uint32_t *stream,
+                           const int64_t *index, int32_t K, float *z, float *radius, int32_t device)
+{
+    if (n < 0 || K < 1 || (n > 0 && (!t || !stream || !index || !z || !radius))) return PSGLD_E_ARG;
+    if (n == 0) return PSGLD_OK;
+    if (hipSetDevice(device) != hipSuccess || !is_gfx950(device)) return PSGLD_E_DEVICE;
+    int64_t *dt = nullptr, *di = nullptr;
+    uint32_t *ds = nullptr;
+    float *dz = nullptr, *dr = nullptr;
+    psgld_status s = PSGLD_OK;
+    const size_t nz = static_cast<size_t>(n) * K * sizeof(float);
+    if (hipMalloc(&dt, n * 8) != hipSuccess || hipMalloc(&di, n * 8) != hipSuccess ||
+        hipMalloc(&ds, n * 4) != hipSuccess || hipMalloc(&dz, nz) != hipSuccess ||
+        hipMalloc(&dr, nz) != hipSuccess) {
+        s = PSGLD_E_NOMEM;
+    } else if (hipMemcpy(dt, t, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(di, index, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(ds, stream, n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+               launch_normals(n, seed, dt, ds, di, K, dz, dr, nullptr) != hipSuccess ||
+               hipMemcpy(z, dz, nz, hipMemcpyDeviceToHost) != hipSuccess ||
+               hipMemcpy(radius, dr, nz, hipMemcpyDeviceToHost) != hipSuccess) {
+        s = PSGLD_E_DEVICE;
+    }
+    (void)hipFree(dt);
+    (void)hipFree(di);
+    (void)hipFree(ds);
+    (void)hipFree(dz);
+    (void)hipFree(dr);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+"""Shared helpers of the GPU-vs-oracle parity tests (not a test module)."""
+import numpy as np
+
+import oracle
+import paper_1506_01418_amd as pkg
+
+# Single-step tolerance for the FP32 path: |x_gpu - x_ref| <= TOL * c_x with
+# c_x = |x_old| + eps (s_p G+_x + |prior'(x_old)|) + sigma R_x (the magnitude of
+# every term that enters the update, computed by the oracle in FP64).
+TOL_FP32 = 1e-5
+
+
+def oracle_config(wl, flags=0):
+    cfg = oracle.Config(**wl.fit_kwargs())
+    cfg.flags = flags
+    return cfg
+
+
+def scaled_error(x_gpu, x_ref, bound):
+    d = np.abs(np.asarray(x_gpu, np.float64) - x_ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(bound > 0, d / bound, np.where(d == 0, 0.0, np.inf))
+    return e
+
+
+def step_parity(wl, steps_before=0, flags=0, sampler=None, **overrides):
+    """Runs the GPU chain `steps_before` iterations, hands its FP32 state to
+    the oracle, then takes one more iteration on both and returns the worst
+    scaled error over W and H (and the sampler)."""
+    s = sampler or pkg.PSGLD.from_workload(wl, test_flags=flags, **overrides)
+    if steps_before:
+        s.step(steps_before, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    Wg, Hg = s.factors()
+    cfg = oracle_config(wl, flags)
+    ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol,
+                      row_piece=overrides.get("row_piece"), col_piece=overrides.get("col_piece"))
+    ch.set_state(Wg, Hg, s.iteration())
+    bW, bH = ch.run(1, bounds=True)
+    s.step(1, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    Wn, Hn = s.factors()
+    eW = scaled_error(Wn, ch.W, bW)
+    eH = scaled_error(Hn, ch.H, bH)
+    return max(float(eW.max(initial=0)), float(eH.max(initial=0))), s

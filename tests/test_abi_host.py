@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+function declared in include/psgld.h is exported, and argument validation of
+psgld_create / psgld_load_coo happens on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1506_01418_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "psgld.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psgld_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert len(names) >= 25
+    L = C.CDLL(pkg.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(pkg.SIGNATURES), set(names) ^ set(pkg.SIGNATURES)
+
+
+def test_default_options():
+    o = pkg.psgld_default_options()
+    assert o.thin == 1 and o.dense_threshold == 0.3 and o.mu_floor == 1e-6 and o.device == 0
+
+
+@pytest.mark.parametrize("I,J,K,B,beta,phi,lw,msg", [
+    (0, 5, 2, 1, 2.0, 1.0, 1.0, "I and J"),
+    (5, 5, 0, 1, 2.0, 1.0, 1.0, "K must"),
+    (5, 5, 300, 1, 2.0, 1.0, 1.0, "K must"),
+    (5, 5, 2, 6, 2.0, 1.0, 1.0, "B must"),
+    (5, 5, 2, 0, 2.0, 1.0, 1.0, "B must"),
+    (5, 5, 2, 2, 2.0, 0.0, 1.0, "phi"),
+    (5, 5, 2, 2, 1.5, 1.0, 1.0, "no Tweedie"),
+    (5, 5, 2, 2, 2.0, 1.0, -1.0, "prior rates"),
+])
+def test_create_rejects_bad_arguments(I, J, K, B, beta, phi, lw, msg):
+    with pytest.raises(pkg.PsgldError) as e:
+        pkg.psgld_create(I, J, K, B, pkg.psgld_likelihood(beta, phi),
+                         pkg.psgld_prior(pkg.PSGLD_PRIOR_GAUSSIAN, lw, 1.0, 0))
+    assert e.value.status == pkg.PSGLD_E_ARG and msg in str(e.value)
+
+
+def test_create_checks_pieces_and_thin():
+    with pytest.raises(pkg.PsgldError, match="non-empty"):
+        pkg.PSGLD(6, 6, 2, 3, row_piece=[0, 0, 1, 1, 1, 1])
+    with pytest.raises(pkg.PsgldError, match="out of range"):
+        pkg.PSGLD(6, 6, 2, 3, col_piece=[0, 0, 1, 1, 2, 3])
+    with pytest.raises(pkg.PsgldError, match="thin"):
+        pkg.PSGLD(6, 6, 2, 3, thin=0)
+
+
+def test_load_validates_on_host_before_device():
+    s = pkg.PSGLD(4, 4, 2, 2, beta=1.0, prior="exponential", mirror=True)
+    with pytest.raises(pkg.PsgldError, match="out of range"):
+        s.load_coo([0, 4], [0, 1], [1.0, 2.0])
+    with pytest.raises(pkg.PsgldError, match="negative"):
+        s.load_coo([0, 1], [0, 1], [1.0, -2.0])
+    with pytest.raises(pkg.PsgldError, match="non-finite"):
+        s.load_coo([0, 1], [0, 1], [1.0, np.nan])
+    g = pkg.PSGLD(4, 4, 2, 2, beta=0.0)
+    with pytest.raises(pkg.PsgldError, match="non-positive"):
+        g.load_coo([0], [0], [0.0])
+    # stepping before loading is a state error
+    with pytest.raises(pkg.PsgldError) as e:
+        s.step(1, 1e-3)
+    assert e.value.status == pkg.PSGLD_E_STATE
+    with pytest.raises(pkg.PsgldError) as e:
+        pkg.psgld_step(s.ctx, 1, pkg.psgld_eps_schedule(1e-3, 1.0, 0.3))
+    assert e.value.status == pkg.PSGLD_E_ARG
+    s.close()
+    g.close()
