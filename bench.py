@@ -134,6 +134,10 @@ def main():
     ev = HipEvents()
     s = pkg.PSGLD.from_workload(wl)
     stream = s.stream()
+    t_tune = time.perf_counter()
+    chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
+    print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
+          file=sys.stderr, flush=True)
     n_p, N = s.part_sizes()
     ho_part = (np.asarray(pkg_pieces(wl, "col"))[wl.hcol] - np.asarray(pkg_pieces(wl, "row"))[wl.hrow]) % wl.B
     ho_p = np.bincount(ho_part, minlength=wl.B)
@@ -190,7 +194,7 @@ def main():
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
                    "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
-                   "heldout_rmse": rmse, "parallelism": "single-gpu"},
+                   "heldout_rmse": rmse, "entries_per_group": chosen, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "sparse_iter_kernel", "avg_launch_us": avg_ms * 1e3,

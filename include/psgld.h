@@ -154,6 +154,20 @@ psgld_status psgld_set_factors(psgld_ctx *ctx, const float *W, const float *H);
  * these iterations is reported as E_NUMERIC by the next synchronising call. */
 psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule *sched);
 
+/* Tunes the work schedule of the coordinate-stored blocks (how many entries
+ * one lane group takes before an item is spread over more groups) on this
+ * context's own data.  With n > 1, each candidate in candidates[0..n) is
+ * timed over `iters` iterations (iters < 1: one cycle of B parts) from the
+ * current state with schedule `sched`; the state is restored afterwards, so
+ * the chain is unchanged, and the fastest candidate is kept and remembered
+ * for this shape (in-process, and in the file named by the environment
+ * variable PSGLD_TUNE_CACHE if set, which later contexts of the same shape
+ * read at load).  With n == 1 the candidate is simply applied.  Results are
+ * bitwise reproducible for a fixed choice; different choices change the FP32
+ * summation order.  *chosen (may be NULL) receives the value kept.  Syncs. */
+psgld_status psgld_tune(psgld_ctx *ctx, const int32_t *candidates, int32_t n, int32_t iters,
+                        const psgld_eps_schedule *sched, int32_t *chosen);
+
 /* Blocks until the context's queued work is done.  E_NUMERIC (with the
  * first iteration index in the message) if a non-finite value appeared. */
 psgld_status psgld_sync(psgld_ctx *ctx);

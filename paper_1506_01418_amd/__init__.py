@@ -78,6 +78,7 @@ SIGNATURES = {
     "psgld_set_factors": ([_P, _P, _P], _ST),
     "psgld_step": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
     "psgld_sync": ([_P], _ST),
+    "psgld_tune": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(psgld_eps_schedule), C.POINTER(C.c_int32)], _ST),
     "psgld_get_factors": ([_P, _P, _P], _ST),
     "psgld_posterior_mean": ([_P, _P, _P], _ST),
     "psgld_posterior_var": ([_P, _P, _P], _ST),
@@ -170,6 +171,13 @@ def psgld_set_factors(ctx, W, H):
 
 def psgld_step(ctx, n_iter, sched: psgld_eps_schedule):
     _check(lib().psgld_step(ctx, int(n_iter), C.byref(sched)), ctx)
+
+
+def psgld_tune(ctx, candidates, iters, sched: psgld_eps_schedule) -> int:
+    cand = _arr(candidates, np.int32)
+    out = C.c_int32()
+    _check(lib().psgld_tune(ctx, _ptr(cand), len(cand), int(iters), C.byref(sched), C.byref(out)), ctx)
+    return out.value
 
 
 def psgld_sync(ctx):
@@ -337,6 +345,9 @@ class PSGLD:
 
     def step(self, n_iter, a, t0=1.0, gamma=0.51):
         psgld_step(self.ctx, n_iter, psgld_eps_schedule(a, t0, gamma))
+
+    def tune(self, a, t0=1.0, gamma=0.51, candidates=(16, 32, 64, 128), iters=0):
+        return psgld_tune(self.ctx, candidates, iters, psgld_eps_schedule(a, t0, gamma))
 
     def sync(self):
         psgld_sync(self.ctx)

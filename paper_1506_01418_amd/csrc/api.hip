@@ -10,8 +10,8 @@
 //    row-sorted for the W items (partner = column) and column-sorted for the
 //    H items (partner = row).  Offsets are prefix sums over (part, row) and
 //    (part, column), so part p's row offsets are a contiguous slice.
-//  * For every part, rows and columns are listed in decreasing order of
-//    their entry count and packed into work-group tasks (see sparse.hip).
+//  * For every part, a work schedule: work-group tasks and per-group item
+//    records (built in schedule.hip).
 //  * FP64 running sums of x and x^2, and FP64 held-out predictive sums.
 #include <hip/hip_runtime.h>
 
@@ -19,7 +19,10 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -32,7 +35,6 @@ using namespace psgld;
 namespace {
 
 thread_local std::string g_create_error;
-constexpr int kEntriesPerGroup = 16;   // target entries per group before splitting an item
 constexpr uint32_t kStateMagic = 0x50534744u;  // "PSGD"
 constexpr uint32_t kStateVersion = 1;
 
@@ -60,6 +62,8 @@ struct psgld_ctx {
     bool loaded = false, factors_set = false, heldout_loaded = false;
 
     std::vector<int32_t> row_piece, col_piece;
+    std::vector<int32_t> pre_r, pre_c;   // entry offsets per (part, row) and (part, column)
+    ScheduleParams sched;
     int64_t N = 0;
     std::vector<int64_t> n_p;
     std::vector<int64_t> task_off, n_tasks;
@@ -71,8 +75,10 @@ struct psgld_ctx {
     int32_t *rowptr = nullptr, *colptr = nullptr;
     Entry *ent_r = nullptr, *ent_c = nullptr;
     int32_t *row_of_entry = nullptr;
-    int32_t *items = nullptr;
-    Task *tasks = nullptr;
+    WgTask *tasks = nullptr;
+    GroupRec *recs = nullptr;
+    float *split_partial = nullptr;
+    int32_t *split_count = nullptr;
     double *sum[2] = {nullptr, nullptr}, *sum2[2] = {nullptr, nullptr};
     int64_t n_kept = 0;
 
@@ -121,6 +127,18 @@ psgld_status dev_alloc(psgld_ctx *c, T **p, size_t count)
     return PSGLD_OK;
 }
 
+void dev_free(psgld_ctx *c, void *p)
+{
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it == c->allocs.end()) return;
+    c->allocs.erase(it);
+    size_t bytes = 0;
+    (void)hipMemPtrGetInfo(p, &bytes);
+    c->bytes -= static_cast<int64_t>(bytes);
+    (void)hipFree(p);
+}
+
 psgld_status ensure_device(psgld_ctx *c)
 {
     if (c->device_ready) return PSGLD_OK;
@@ -160,32 +178,96 @@ int32_t part_of(const psgld_ctx *c, int32_t i, int32_t j)
     return (c->col_piece[j] - c->row_piece[i] + c->B) % c->B;
 }
 
-int next_pow2(int64_t v)
+// Builds every part's work schedule for c->sched and uploads it, replacing
+// any previous one.
+psgld_status upload_schedule(psgld_ctx *c)
 {
-    int p = 1;
-    while (p < v) p *= 2;
-    return p;
+    const int64_t I = c->I, J = c->J;
+    const int32_t B = c->B;
+    std::vector<WgTask> tasks;
+    std::vector<GroupRec> recs;
+    int32_t max_splits = 0;
+    c->task_off.assign(B, 0);
+    c->n_tasks.assign(B, 0);
+    for (int32_t p = 0; p < B; ++p) {
+        PartSchedule ps;
+        build_part_schedule(c->pre_r.data() + static_cast<size_t>(p) * I, c->pre_c.data() + static_cast<size_t>(p) * J,
+                            I, J, c->row_piece, c->col_piece, B, p, c->lpg, c->sched, ps);
+        c->task_off[p] = static_cast<int64_t>(tasks.size());
+        c->n_tasks[p] = static_cast<int64_t>(ps.tasks.size());
+        tasks.insert(tasks.end(), ps.tasks.begin(), ps.tasks.end());
+        recs.insert(recs.end(), ps.recs.begin(), ps.recs.end());
+        max_splits = std::max(max_splits, ps.n_splits);
+    }
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    dev_free(c, c->tasks);
+    dev_free(c, c->recs);
+    dev_free(c, c->split_partial);
+    dev_free(c, c->split_count);
+    c->tasks = nullptr;
+    c->recs = nullptr;
+    c->split_partial = nullptr;
+    c->split_count = nullptr;
+    psgld_status s;
+    if ((s = upload(c, &c->tasks, tasks))) return s;
+    if ((s = upload(c, &c->recs, recs))) return s;
+    if ((s = dev_alloc(c, &c->split_partial, static_cast<size_t>(max_splits) * c->Kp))) return s;
+    if ((s = dev_alloc(c, &c->split_count, static_cast<size_t>(max_splits)))) return s;
+    HIPTRY(c, hipMemset(c->split_count, 0, std::max<int32_t>(max_splits, 1) * sizeof(int32_t)));
+    return PSGLD_OK;
 }
 
-// Splits one side's size-sorted item list of one part into tasks.
-void build_tasks(const std::vector<int64_t> &cnt_sorted, int32_t side, int32_t first_off,
-                 int Q, std::vector<Task> &out)
+// Shape signature of a context for the tuning cache: sizes, rank, blocks,
+// likelihood branch and the longest row and column of any part.
+std::string tune_key(const psgld_ctx *c)
 {
-    const int64_t n = static_cast<int64_t>(cnt_sorted.size());
-    int64_t pos = 0;
-    while (pos < n) {
-        const int64_t need = (cnt_sorted[pos] + kEntriesPerGroup - 1) / kEntriesPerGroup;
-        const int G = std::min(Q, next_pow2(std::max<int64_t>(need, 1)));
-        const int per = Q / G;
-        int64_t end = pos;
-        while (end < n && end - pos < per) {
-            const int64_t nd = (cnt_sorted[end] + kEntriesPerGroup - 1) / kEntriesPerGroup;
-            if (std::min(Q, next_pow2(std::max<int64_t>(nd, 1))) != G) break;
-            ++end;
+    int32_t max_r = 0, max_c = 0;
+    for (size_t k = 0; k + 1 < c->pre_r.size(); ++k) max_r = std::max(max_r, c->pre_r[k + 1] - c->pre_r[k]);
+    for (size_t k = 0; k + 1 < c->pre_c.size(); ++k) max_c = std::max(max_c, c->pre_c[k + 1] - c->pre_c[k]);
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "gfx950:I%lld:J%lld:K%d:B%d:N%lld:lik%d:r%d:c%d", static_cast<long long>(c->I),
+                  static_cast<long long>(c->J), c->K, c->B, static_cast<long long>(c->N), c->lik_kind, max_r, max_c);
+    return buf;
+}
+
+std::mutex g_tune_mutex;
+std::map<std::string, int> g_tune_memo;
+
+// Entries-per-group remembered for this signature in this process, else in
+// the file named by PSGLD_TUNE_CACHE (lines "<signature> <value>"), else dflt.
+int cached_entries_per_group(const psgld_ctx *c, int dflt)
+{
+    const std::string key = tune_key(c);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_memo.find(key);
+    if (it != g_tune_memo.end()) return it->second;
+    if (const char *path = std::getenv("PSGLD_TUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "r")) {
+            char k[256];
+            int v = 0;
+            int found = -1;
+            while (std::fscanf(f, "%255s %d", k, &v) == 2)
+                if (key == k) found = v;
+            std::fclose(f);
+            if (found > 0) {
+                g_tune_memo[key] = found;
+                return found;
+            }
         }
-        out.push_back(Task{side, first_off + static_cast<int32_t>(pos),
-                           static_cast<int32_t>(end - pos), G});
-        pos = end;
+    }
+    return dflt;
+}
+
+void remember_entries_per_group(const psgld_ctx *c, int value)
+{
+    const std::string key = tune_key(c);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_memo[key] = value;
+    if (const char *path = std::getenv("PSGLD_TUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s %d\n", key.c_str(), value);
+            std::fclose(f);
+        }
     }
 }
 
@@ -217,52 +299,29 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
             ec[kc] = Entry{row[e], val[e]};
         }
     }
-    auto by_idx = [](const Entry &a, const Entry &b) { return a.idx < b.idx; };
+    auto by_idx = [](const Entry &a, const Entry &b) { return a.off < b.off; };
     for (size_t k = 0; k + 1 < pre_r.size(); ++k) {
         if (pre_r[k + 1] - pre_r[k] > 1) {
             std::sort(er.begin() + pre_r[k], er.begin() + pre_r[k + 1], by_idx);
             for (int32_t m = pre_r[k] + 1; m < pre_r[k + 1]; ++m)
-                if (er[m].idx == er[m - 1].idx) {
+                if (er[m].off == er[m - 1].off) {
                     const int64_t i = static_cast<int64_t>(k % I);
                     return c->fail(PSGLD_E_ARG, "duplicate training entry (" + std::to_string(i) +
-                                                    ", " + std::to_string(er[m].idx) + ")");
+                                                    ", " + std::to_string(er[m].off) + ")");
                 }
         }
     }
     for (size_t k = 0; k + 1 < pre_c.size(); ++k)
         if (pre_c[k + 1] - pre_c[k] > 1) std::sort(ec.begin() + pre_c[k], ec.begin() + pre_c[k + 1], by_idx);
+    // partner indices -> offsets into the factor arrays; pad the arrays
+    for (auto &x : er) x.off *= c->Kp;
+    for (auto &x : ec) x.off *= c->Kp;
+    er.resize(static_cast<size_t>(nnz) + kEntryPad, Entry{0, 0.f});
+    ec.resize(static_cast<size_t>(nnz) + kEntryPad, Entry{0, 0.f});
 
     c->N = nnz;
     c->n_p.assign(B, 0);
     for (int32_t p = 0; p < B; ++p) c->n_p[p] = pre_r[static_cast<size_t>(p + 1) * I] - pre_r[static_cast<size_t>(p) * I];
-
-    // items sorted by decreasing entry count (ties by index) and their tasks
-    const int Q = sparse_block_threads() / c->lpg;
-    std::vector<int32_t> items(static_cast<size_t>(B) * (I + J));
-    std::vector<Task> tasks;
-    c->task_off.assign(B, 0);
-    c->n_tasks.assign(B, 0);
-    for (int32_t p = 0; p < B; ++p) {
-        int32_t *it = items.data() + static_cast<size_t>(p) * (I + J);
-        std::vector<Task> tp;
-        for (int side = 0; side < 2; ++side) {
-            const int64_t n = side == 0 ? I : J;
-            const int32_t *pre = side == 0 ? pre_r.data() + static_cast<size_t>(p) * I
-                                           : pre_c.data() + static_cast<size_t>(p) * J;
-            int32_t *lst = it + (side == 0 ? 0 : I);
-            std::iota(lst, lst + n, 0);
-            std::stable_sort(lst, lst + n, [pre](int32_t a, int32_t b) {
-                return pre[a + 1] - pre[a] > pre[b + 1] - pre[b];
-            });
-            std::vector<int64_t> cnt(n);
-            for (int64_t m = 0; m < n; ++m) cnt[m] = pre[lst[m] + 1] - pre[lst[m]];
-            build_tasks(cnt, side, side == 0 ? 0 : static_cast<int32_t>(I), Q, tp);
-        }
-        std::stable_sort(tp.begin(), tp.end(), [](const Task &a, const Task &b) { return a.G > b.G; });
-        c->task_off[p] = static_cast<int64_t>(tasks.size());
-        c->n_tasks[p] = static_cast<int64_t>(tp.size());
-        tasks.insert(tasks.end(), tp.begin(), tp.end());
-    }
 
     psgld_status s;
     if ((s = upload(c, &c->rowptr, pre_r))) return s;
@@ -270,15 +329,13 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
     if ((s = upload(c, &c->ent_r, er))) return s;
     if ((s = upload(c, &c->ent_c, ec))) return s;
     if ((s = upload(c, &c->row_of_entry, rows_of))) return s;
-    if ((s = upload(c, &c->items, items))) return s;
-    if ((s = upload(c, &c->tasks, tasks))) return s;
 
     const size_t nw = static_cast<size_t>(I) * c->Kp, nh = static_cast<size_t>(J) * c->Kp;
     for (int b = 0; b < 2; ++b) {
-        if ((s = dev_alloc(c, &c->W[b], nw))) return s;
-        if ((s = dev_alloc(c, &c->H[b], nh))) return s;
-        HIPTRY(c, hipMemset(c->W[b], 0, nw * sizeof(float)));
-        HIPTRY(c, hipMemset(c->H[b], 0, nh * sizeof(float)));
+        if ((s = dev_alloc(c, &c->W[b], nw + kFactorPad))) return s;
+        if ((s = dev_alloc(c, &c->H[b], nh + kFactorPad))) return s;
+        HIPTRY(c, hipMemset(c->W[b], 0, (nw + kFactorPad) * sizeof(float)));
+        HIPTRY(c, hipMemset(c->H[b], 0, (nh + kFactorPad) * sizeof(float)));
     }
     for (int side = 0; side < 2; ++side) {
         const size_t n = side == 0 ? nw : nh;
@@ -291,6 +348,10 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
     if ((s = dev_alloc(c, &c->ll_partials, c->ll_blocks))) return s;
     if ((s = dev_alloc(c, &c->ll_out, 1))) return s;
     c->part_visits.assign(B, 0);
+    c->pre_r.swap(pre_r);
+    c->pre_c.swap(pre_c);
+    c->sched.entries_per_group = cached_entries_per_group(c, c->sched.entries_per_group);
+    if ((s = upload_schedule(c))) return s;
     c->loaded = true;
     return PSGLD_OK;
 }
@@ -345,6 +406,73 @@ psgld_status fetch_factor(psgld_ctx *c, const TDev *dev, int64_t rows, bool tran
     return PSGLD_OK;
 }
 
+// Enqueues iteration t (part t mod B) reading buffer `cur`.  With
+// bookkeeping off (tuning trials) no moments, held-out sums or visit counts
+// are touched.
+psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule *sched, bool bookkeeping)
+{
+    const int64_t I = c->I, J = c->J;
+    const int32_t p = static_cast<int32_t>(t % c->B);
+    const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(t), -sched->gamma);
+    SparseIterArgs a{};
+    a.x_old[0] = c->W[c->cur];
+    a.x_old[1] = c->H[c->cur];
+    a.x_new[0] = c->W[c->cur ^ 1];
+    a.x_new[1] = c->H[c->cur ^ 1];
+    a.ptr[0] = c->rowptr + static_cast<size_t>(p) * I;
+    a.ptr[1] = c->colptr + static_cast<size_t>(p) * J;
+    a.ent[0] = c->ent_r;
+    a.ent[1] = c->ent_c;
+    a.tasks = c->tasks + c->task_off[p];
+    a.recs = c->recs + static_cast<size_t>(c->task_off[p]) * (sparse_block_threads() / c->lpg);
+    a.n_tasks = static_cast<int32_t>(c->n_tasks[p]);
+    a.split_partial = c->split_partial;
+    a.split_count = c->split_count;
+    a.K = c->K;
+    a.Kp = c->Kp;
+    a.nq = c->nq;
+    a.eps = static_cast<float>(eps);
+    a.sigma = static_cast<float>(std::sqrt(2.0 * eps));
+    a.scale = c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
+    a.lambda[0] = static_cast<float>(c->prior.lambda_w);
+    a.lambda[1] = static_cast<float>(c->prior.lambda_h);
+    a.inv_phi = static_cast<float>(1.0 / c->lik.phi);
+    a.beta = static_cast<float>(c->lik.beta);
+    a.mu_floor = static_cast<float>(c->opt.mu_floor);
+    a.seed_lo = static_cast<uint32_t>(c->opt.seed);
+    a.seed_hi = static_cast<uint32_t>(c->opt.seed >> 32);
+    a.t = static_cast<uint32_t>(t);
+    a.mirror = c->prior.mirror ? 1 : 0;
+    a.prior_kind = c->prior.kind;
+    a.flags = c->opt.test_flags;
+    const bool post = bookkeeping && t >= c->opt.burn_in;
+    a.do_moments = post && (t - c->opt.burn_in) % c->opt.thin == 0;
+    for (int side = 0; side < 2; ++side) {
+        a.sum[side] = c->sum[side];
+        a.sum2[side] = c->sum2[side];
+    }
+    a.do_heldout = post && c->n_ho > 0;
+    a.ho_ptr = c->ho_ptr ? c->ho_ptr + static_cast<size_t>(p) * I : nullptr;
+    a.ho_ent = c->ho_ent;
+    a.ho_sum = c->ho_sum;
+    a.nonfinite = c->nonfinite;
+    HIPTRY(c, launch_sparse_iter(a, c->lik_kind, c->lpg, c->stream));
+    if (a.do_moments) c->n_kept++;
+    if (a.do_heldout) c->part_visits[p]++;
+    c->cur ^= 1;
+    return PSGLD_OK;
+}
+
+psgld_status check_schedule(psgld_ctx *c, const psgld_eps_schedule *sched)
+{
+    if (!sched) return c->fail(PSGLD_E_ARG, "schedule is required");
+    if (!(sched->a > 0.0) || !std::isfinite(sched->a)) return c->fail(PSGLD_E_ARG, "eps: a must be > 0");
+    if (!(sched->gamma == 0.0 || (sched->gamma > 0.5 && sched->gamma <= 1.0)))
+        return c->fail(PSGLD_E_ARG, "eps: gamma must be in (0.5, 1] (Eq. (4)) or 0");
+    if (sched->gamma > 0.0 && !(sched->t0 > 0.0)) return c->fail(PSGLD_E_ARG, "eps: t0 must be > 0");
+    return PSGLD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -378,6 +506,8 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (!lik || !prior) return bad("likelihood and prior are required");
     if (I < 1 || J < 1 || I > INT32_MAX || J > INT32_MAX) return bad("I and J must be in [1, 2^31)");
     if (K < 1 || K > 256) return bad("K must be in [1, 256]");
+    if ((I + 1) * ((K + 3) / 4 * 4) >= INT32_MAX || (J + 1) * ((K + 3) / 4 * 4) >= INT32_MAX)
+        return bad("I * K and J * K must stay below 2^31");
     if (B < 1 || B > I || B > J) return bad("B must be in [1, min(I, J)]");
     if (!(lik->phi > 0.0) || !std::isfinite(lik->phi) || !std::isfinite(lik->beta)) return bad("phi must be > 0, beta finite");
     if (lik->beta > 1.0 && lik->beta < 2.0) return bad("no Tweedie model exists for 1 < beta < 2");
@@ -504,7 +634,8 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     {
         std::vector<int32_t> fill(pre.begin(), pre.end() - 1);
         for (int64_t e = 0; e < n; ++e)
-            he[fill[static_cast<size_t>(c->ho_part[e]) * I + row[e]]++] = HeldEntry{col[e], static_cast<int32_t>(e)};
+            he[fill[static_cast<size_t>(c->ho_part[e]) * I + row[e]]++] =
+                HeldEntry{col[e] * c->Kp, static_cast<int32_t>(e)};
     }
     // distinct cells, disjoint from the training entries
     std::vector<int32_t> rp(static_cast<size_t>(B) * I + 1);
@@ -513,12 +644,12 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     if (c->N) HIPTRY(c, hipMemcpy(er.data(), c->ent_r, er.size() * sizeof(Entry), hipMemcpyDeviceToHost));
     for (size_t k = 0; k + 1 < pre.size(); ++k) {
         std::sort(he.begin() + pre[k], he.begin() + pre[k + 1],
-                  [](const HeldEntry &a, const HeldEntry &b) { return a.col < b.col; });
+                  [](const HeldEntry &a, const HeldEntry &b) { return a.off < b.off; });
         for (int32_t m = pre[k]; m < pre[k + 1]; ++m) {
-            if (m > pre[k] && he[m].col == he[m - 1].col) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
+            if (m > pre[k] && he[m].off == he[m - 1].off) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
             const Entry *b0 = er.data() + rp[k], *b1 = er.data() + rp[k + 1];
-            const Entry *f = std::lower_bound(b0, b1, he[m].col, [](const Entry &a, int32_t v) { return a.idx < v; });
-            if (f != b1 && f->idx == he[m].col)
+            const Entry *f = std::lower_bound(b0, b1, he[m].off, [](const Entry &a, int32_t v) { return a.off < v; });
+            if (f != b1 && f->off == he[m].off)
                 return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
         }
     }
@@ -566,66 +697,79 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
 {
     if (!c) return PSGLD_E_ARG;
     c->err.clear();
-    if (!sched) return c->fail(PSGLD_E_ARG, "schedule is required");
+    psgld_status s = check_schedule(c, sched);
+    if (s) return s;
     if (n_iter < 0) return c->fail(PSGLD_E_ARG, "n_iter must be >= 0");
-    if (!(sched->a > 0.0) || !std::isfinite(sched->a)) return c->fail(PSGLD_E_ARG, "eps: a must be > 0");
-    if (!(sched->gamma == 0.0 || (sched->gamma > 0.5 && sched->gamma <= 1.0)))
-        return c->fail(PSGLD_E_ARG, "eps: gamma must be in (0.5, 1] (Eq. (4)) or 0");
-    if (sched->gamma > 0.0 && !(sched->t0 > 0.0)) return c->fail(PSGLD_E_ARG, "eps: t0 must be > 0");
     if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
     if (c->t + n_iter >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
     HIPTRY(c, hipSetDevice(c->opt.device));
-    const int64_t I = c->I, J = c->J;
     for (int64_t it = 0; it < n_iter; ++it) {
-        const int64_t t = c->t;
-        const int32_t p = static_cast<int32_t>(t % c->B);
-        const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(t), -sched->gamma);
-        SparseIterArgs a{};
-        a.x_old[0] = c->W[c->cur];
-        a.x_old[1] = c->H[c->cur];
-        a.x_new[0] = c->W[c->cur ^ 1];
-        a.x_new[1] = c->H[c->cur ^ 1];
-        a.ptr[0] = c->rowptr + static_cast<size_t>(p) * I;
-        a.ptr[1] = c->colptr + static_cast<size_t>(p) * J;
-        a.ent[0] = c->ent_r;
-        a.ent[1] = c->ent_c;
-        a.items = c->items + static_cast<size_t>(p) * (I + J);
-        a.tasks = c->tasks + c->task_off[p];
-        a.n_tasks = static_cast<int32_t>(c->n_tasks[p]);
-        a.K = c->K;
-        a.Kp = c->Kp;
-        a.nq = c->nq;
-        a.eps = static_cast<float>(eps);
-        a.sigma = static_cast<float>(std::sqrt(2.0 * eps));
-        a.scale = c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
-        a.lambda[0] = static_cast<float>(c->prior.lambda_w);
-        a.lambda[1] = static_cast<float>(c->prior.lambda_h);
-        a.inv_phi = static_cast<float>(1.0 / c->lik.phi);
-        a.beta = static_cast<float>(c->lik.beta);
-        a.mu_floor = static_cast<float>(c->opt.mu_floor);
-        a.seed_lo = static_cast<uint32_t>(c->opt.seed);
-        a.seed_hi = static_cast<uint32_t>(c->opt.seed >> 32);
-        a.t = static_cast<uint32_t>(t);
-        a.mirror = c->prior.mirror ? 1 : 0;
-        a.prior_kind = c->prior.kind;
-        a.flags = c->opt.test_flags;
-        const bool post = t >= c->opt.burn_in;
-        a.do_moments = post && (t - c->opt.burn_in) % c->opt.thin == 0;
-        for (int side = 0; side < 2; ++side) {
-            a.sum[side] = c->sum[side];
-            a.sum2[side] = c->sum2[side];
-        }
-        a.do_heldout = post && c->n_ho > 0;
-        a.ho_ptr = c->ho_ptr ? c->ho_ptr + static_cast<size_t>(p) * I : nullptr;
-        a.ho_ent = c->ho_ent;
-        a.ho_sum = c->ho_sum;
-        a.nonfinite = c->nonfinite;
-        HIPTRY(c, launch_sparse_iter(a, c->lik_kind, c->lpg, c->stream));
-        if (a.do_moments) c->n_kept++;
-        if (a.do_heldout) c->part_visits[p]++;
-        c->cur ^= 1;
-        c->t = t + 1;
+        if ((s = launch_iteration(c, c->t, sched, true))) return s;
+        c->t += 1;
     }
+    return PSGLD_OK;
+}
+
+psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int32_t iters,
+                        const psgld_eps_schedule *sched, int32_t *chosen)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+    if (n < 1 || !candidates) return c->fail(PSGLD_E_ARG, "at least one candidate is required");
+    for (int32_t k = 0; k < n; ++k)
+        if (candidates[k] < 1) return c->fail(PSGLD_E_ARG, "candidates must be >= 1");
+    psgld_status s;
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    int best = candidates[0];
+    if (n > 1) {
+        if ((s = check_schedule(c, sched))) return s;
+        if ((s = sync_and_check(c))) return s;
+        if (iters < 1) iters = c->B;
+        // trials run on copies of the state, from the context's current t
+        const size_t nw = static_cast<size_t>(c->I) * c->Kp + kFactorPad, nh = static_cast<size_t>(c->J) * c->Kp + kFactorPad;
+        const int cur0 = c->cur;
+        float *w0 = nullptr, *h0 = nullptr;
+        if ((s = dev_alloc(c, &w0, nw)) || (s = dev_alloc(c, &h0, nh))) return s;
+        HIPTRY(c, hipMemcpyAsync(w0, c->W[cur0], nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPTRY(c, hipMemcpyAsync(h0, c->H[cur0], nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        hipEvent_t e0, e1;
+        HIPTRY(c, hipEventCreate(&e0));
+        HIPTRY(c, hipEventCreate(&e1));
+        float best_ms = 0.f;
+        for (int32_t k = 0; k < n; ++k) {
+            c->sched.entries_per_group = candidates[k];
+            if ((s = upload_schedule(c))) return s;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {   // first pass warms up
+                HIPTRY(c, hipMemcpyAsync(c->W[cur0], w0, nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+                HIPTRY(c, hipMemcpyAsync(c->H[cur0], h0, nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+                c->cur = cur0;
+                HIPTRY(c, hipEventRecord(e0, c->stream));
+                for (int32_t it = 0; it < iters; ++it)
+                    if ((s = launch_iteration(c, c->t + it, sched, false))) return s;
+                HIPTRY(c, hipEventRecord(e1, c->stream));
+                HIPTRY(c, hipEventSynchronize(e1));
+                HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
+            }
+            if (k == 0 || ms < best_ms) {
+                best_ms = ms;
+                best = candidates[k];
+            }
+        }
+        HIPTRY(c, hipMemcpyAsync(c->W[cur0], w0, nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPTRY(c, hipMemcpyAsync(c->H[cur0], h0, nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        c->cur = cur0;
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        dev_free(c, w0);
+        dev_free(c, h0);
+        remember_entries_per_group(c, best);
+    }
+    c->sched.entries_per_group = best;
+    if ((s = upload_schedule(c))) return s;
+    if (chosen) *chosen = best;
     return PSGLD_OK;
 }
 

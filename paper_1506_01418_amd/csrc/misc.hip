@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * kLLThreads + threadIdx.x; e < n;
          e += static_cast<int64_t>(gridDim.x) * kLLThreads) {
         const float *w = W + static_cast<size_t>(row_of_entry[e]) * Kp;
-        const float *h = Hs + static_cast<size_t>(ent[e].idx) * Kp;
+        const float *h = Hs + ent[e].off;
         double mu = 0.0;
         for (int k = 0; k < K; ++k) mu += static_cast<double>(w[k]) * static_cast<double>(h[k]);
         if (beta < 2.0 && mu < mu_floor) mu = mu_floor;

@@ -8,15 +8,16 @@
 //
 //  * an "item" is a row of W (side 0) or a column of H (side 1);
 //  * the part's entries are stored twice, row-sorted (for W items) and
-//    column-sorted (for H items), so each item's gradient is a plain
-//    sequential sum over a contiguous run of entries -- no atomics;
+//    column-sorted (for H items), so each item's gradient is a sequential
+//    sum over a contiguous run of entries -- no atomics on values;
 //  * a group of LPG lanes owns one item, each lane four consecutive k
 //    (a float4), so a K-length dot product is four FMAs plus a log2(LPG)
-//    step butterfly across the group;
-//  * long items are split over G groups of the same work-group, whose
-//    partial gradients are combined in LDS in a fixed order;
+//    step butterfly across the group (DPP inside 16-lane rows);
+//  * long items are split over G groups of one work-group, combined in LDS
+//    in a fixed order, and the longest over several work-groups, combined
+//    in a fixed order by whichever share finishes last;
 //  * the Langevin step, noise, prior and mirroring are applied by the item's
-//    first group right after its gradient, into the other ping-pong buffer;
+//    lead group right after its gradient, into the other ping-pong buffer;
 //    the old buffers are only read, so no item waits for another.
 #include "internal.hpp"
 #include "noise.hpp"
@@ -25,14 +26,53 @@ namespace psgld {
 namespace {
 
 constexpr int kBlockThreads = 256;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the LPG lanes of a group; every lane gets the same bits (each
+// stage adds a symmetric pair of lanes).  xor 1 and xor 2 are quad
+// permutations, then half-row and row mirrors pair the 4- and 8-lane halves
+// of a 16-lane row; across rows a swizzle (xor 16) and a permute (xor 32).
 template <int LPG>
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int off = LPG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPG);
+    if constexpr (LPG >= 2) v += dpp<0xB1>(v);
+    if constexpr (LPG >= 4) v += dpp<0x4E>(v);
+    if constexpr (LPG >= 8) v += dpp<0x141>(v);
+    if constexpr (LPG >= 16) v += dpp<0x140>(v);
+    if constexpr (LPG >= 32) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    if constexpr (LPG >= 64) v += __shfl_xor(v, 32);
     return v;
+}
+
+// The same butterfly applied to N independent values stage by stage, so
+// consecutive DPP operations never depend on each other.
+template <int LPG, int N>
+__device__ __forceinline__ void group_sum_n(float (&v)[N])
+{
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 2) v[n] += dpp<0xB1>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 4) v[n] += dpp<0x4E>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 8) v[n] += dpp<0x141>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 16) v[n] += dpp<0x140>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 32) v[n] += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v[n]), 0x401F));
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if constexpr (LPG >= 64) v[n] += __shfl_xor(v[n], 32);
 }
 
 __device__ __forceinline__ float dot4(const float4 &a, const float4 &b)
@@ -46,6 +86,14 @@ __device__ __forceinline__ void axpy4(float4 &acc, float r, const float4 &o)
     acc.y += r * o.y;
     acc.z += r * o.z;
     acc.w += r * o.w;
+}
+
+__device__ __forceinline__ void add4(float4 &acc, const float4 &o)
+{
+    acc.x += o.x;
+    acc.y += o.y;
+    acc.z += o.z;
+    acc.w += o.w;
 }
 
 // d/dmu log TW(v; mu, phi, beta) = (v - mu) mu^(beta-2) / phi, with the mean
@@ -66,92 +114,89 @@ __device__ __forceinline__ float residual(float v, float mu, const SparseIterArg
 
 __device__ __forceinline__ float4 load4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
-template <int LPG, int LIK>
-__global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterArgs a)
+// One group's view of its current item: the item's own row (x), and the
+// first batch of its entry records.
+struct ItemStart {
+    float4 x;
+    Entry first[kUnroll];
+};
+
+__device__ __forceinline__ ItemStart start_item(const SparseIterArgs &a, const WgTask &task,
+                                                const GroupRec &rec, int lane, bool qlane)
 {
-    __shared__ float4 partial[kBlockThreads];
-    const int tid = threadIdx.x;
-    const int g = tid / LPG;
-    const int lane = tid % LPG;
-    const Task task = a.tasks[blockIdx.x];
-    const int side = task.side;
-    const int G = task.G;
-    const int slot = g / G;
-    const int sub = g % G;
-    const bool active = slot < task.count;
-    const int item = active ? a.items[task.first + slot] : 0;
-    const int Kp = a.Kp;
-    const bool qlane = lane < a.nq;
-    const float *__restrict__ own = a.x_old[side];
-    const float *__restrict__ other = a.x_old[side ^ 1];
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    ItemStart st;
+    st.x = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rec.item >= 0 && qlane)
+        st.x = load4(a.x_old[task.side] + static_cast<size_t>(rec.item) * a.Kp + 4 * lane);
+    const Entry *ent = a.ent[task.side];
+    const int s0 = rec.item >= 0 ? rec.s0 : 0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) st.first[u] = ent[s0 + u];
+    return st;
+}
 
-    float4 x = zero;
-    if (active && qlane) x = load4(own + static_cast<size_t>(item) * Kp + 4 * lane);
-
-    int s0 = 0, s1 = 0;
-    if (active) {
-        const int beg = a.ptr[side][item];
-        const int n = a.ptr[side][item + 1] - beg;
-        s0 = beg + static_cast<int>((static_cast<long long>(n) * sub) / G);
-        s1 = beg + static_cast<int>((static_cast<long long>(n) * (sub + 1)) / G);
-    }
-
-    // Gradient of the likelihood over this group's share of the item's entries.
-    const Entry *__restrict__ ent = a.ent[side];
-    float4 acc = zero;
+// Gradient of the likelihood over the group's entries [s0, s1).  Full
+// batches of kUnroll entries run without masks: lanes past ceil(K/4) have
+// x = 0, read one row ahead (the factor arrays are padded) and never store;
+// the next batch's entry records (arrays padded too) are fetched while the
+// current batch is reduced.  The tail runs one entry at a time.
+template <int LPG, int LIK>
+__device__ __forceinline__ float4 item_gradient(const SparseIterArgs &a, const WgTask &task,
+                                                const GroupRec &rec, const ItemStart &st, int lane)
+{
+    const float4 x = st.x;
+    const Entry *__restrict__ ent = a.ent[task.side];
+    const float *other_lane = a.x_old[task.side ^ 1] + 4 * lane;
+    const int s0 = rec.s0, s1 = rec.item >= 0 ? rec.s1 : rec.s0;
+    const int full_end = s0 + (s1 - s0) / kUnroll * kUnroll;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int e = s0;
-    for (; e + kUnroll <= s1; e += kUnroll) {
-        Entry en[kUnroll];
-        float4 o[kUnroll];
+    if (e < full_end) {
+        Entry cur[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) en[u] = ent[e + u];
+        for (int u = 0; u < kUnroll; ++u) cur[u] = st.first[u];
+        for (; e < full_end; e += kUnroll) {
+            float4 o[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            o[u] = qlane ? load4(other + static_cast<size_t>(en[u].idx) * Kp + 4 * lane) : zero;
+            for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
+            Entry nxt[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const float mu = group_sum<LPG>(dot4(x, o[u]));
-            axpy4(acc, residual<LIK>(en[u].val, mu, a), o[u]);
+            for (int u = 0; u < kUnroll; ++u) nxt[u] = ent[e + kUnroll + u];
+            float mu[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
+            group_sum_n<LPG, kUnroll>(mu);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
         }
     }
     for (; e < s1; ++e) {
         const Entry en = ent[e];
-        const float4 o = qlane ? load4(other + static_cast<size_t>(en.idx) * Kp + 4 * lane) : zero;
+        const float4 o = load4(other_lane + en.off);
         const float mu = group_sum<LPG>(dot4(x, o));
         axpy4(acc, residual<LIK>(en.val, mu, a), o);
     }
+    return acc;
+}
 
-    // Long items: combine the G partial sums in a fixed order.
-    if (G > 1) {
-        partial[tid] = acc;
-        __syncthreads();
-        if (sub == 0) {
-            acc = zero;
-            for (int s = 0; s < G; ++s) {
-                const float4 p = partial[(g + s) * LPG + lane];
-                acc.x += p.x;
-                acc.y += p.y;
-                acc.z += p.z;
-                acc.w += p.w;
-            }
-        }
-    }
-    if (!active || sub != 0) return;
-
-    // Held-out predictive sums at the state entering this iteration.
+// Held-out sums, then the Langevin step of the item's k = 4 lane .. 4 lane + 3
+// with its full gradient g, by the item's lead group.
+template <int LPG>
+__device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, int item, float4 x,
+                                            float4 g, int lane, bool qlane)
+{
     if (side == 0 && a.do_heldout) {
+        const float *other_lane = a.x_old[1] + 4 * lane;
         const int hb = a.ho_ptr[item], he = a.ho_ptr[item + 1];
         for (int h = hb; h < he; ++h) {
             const HeldEntry c = a.ho_ent[h];
-            const float4 o = qlane ? load4(other + static_cast<size_t>(c.col) * Kp + 4 * lane) : zero;
-            const float mu = group_sum<LPG>(dot4(x, o));
+            const float mu = group_sum<LPG>(dot4(x, load4(other_lane + c.off)));
             if (lane == 0) a.ho_sum[c.slot] += static_cast<double>(mu);
         }
     }
     if (!qlane) return;
-
-    // Langevin step for k = 4 lane .. 4 lane + 3.
     const bool frozen = (a.flags & (side == 0 ? PSGLD_TEST_FREEZE_W : PSGLD_TEST_FREEZE_H)) != 0;
     const bool noisy = !frozen && !(a.flags & PSGLD_TEST_NOISE_OFF);
     float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -164,7 +209,7 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterAr
         z[3] = nz.z[3];
     }
     const float xo[4] = {x.x, x.y, x.z, x.w};
-    const float gr[4] = {acc.x, acc.y, acc.z, acc.w};
+    const float gr[4] = {g.x, g.y, g.z, g.w};
     const float lam = a.lambda[side];
     float xn[4];
     bool finite = true;
@@ -181,19 +226,104 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterAr
         finite = finite && isfinite(v);
         xn[c] = v;
     }
-    const size_t off = static_cast<size_t>(item) * Kp + 4 * lane;
+    const size_t off = static_cast<size_t>(item) * a.Kp + 4 * lane;
     *reinterpret_cast<float4 *>(a.x_new[side] + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
     if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(a.t));
     if (a.do_moments) {
-        double *s = a.sum[side] + off;
-        double *s2 = a.sum2[side] + off;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double v = static_cast<double>(xn[c]);
-            s[c] += v;
-            s2[c] += v * v;
+        double2 *s = reinterpret_cast<double2 *>(a.sum[side] + off);
+        double2 *s2 = reinterpret_cast<double2 *>(a.sum2[side] + off);
+        const double d0 = xn[0], d1 = xn[1], d2 = xn[2], d3 = xn[3];
+        double2 p0 = s[0], p1 = s[1], q0 = s2[0], q1 = s2[1];
+        p0.x += d0;
+        p0.y += d1;
+        p1.x += d2;
+        p1.y += d3;
+        q0.x += d0 * d0;
+        q0.y += d1 * d1;
+        q1.x += d2 * d2;
+        q1.y += d3 * d3;
+        s[0] = p0;
+        s[1] = p1;
+        s2[0] = q0;
+        s2[1] = q1;
+    }
+}
+
+// One work-group per task.  The task's records, then each group's own row
+// and entries, then its partner rows are fetched; the item's lead group
+// applies the update.
+template <int LPG, int LIK>
+__global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterArgs a)
+{
+    constexpr int Q = kBlockThreads / LPG;
+    __shared__ float4 partial[kBlockThreads];
+    __shared__ int is_last;
+    const int tid = threadIdx.x;
+    const int g = tid / LPG;
+    const int lane = tid % LPG;
+    const bool qlane = lane < a.nq;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int t = blockIdx.x;
+    const WgTask task = a.tasks[t];
+    const GroupRec rec = a.recs[static_cast<size_t>(t) * Q + g];
+    const ItemStart st = start_item(a, task, rec, lane, qlane);
+    const int G = 1 << task.glog2;
+    const int sub = g & (G - 1);
+    float4 acc = item_gradient<LPG, LIK>(a, task, rec, st, lane);
+
+    // Items split over G groups: combine the partial sums in a fixed order.
+    if (G > 1) {
+        partial[tid] = acc;
+        __syncthreads();
+        if (sub == 0) {
+            acc = zero;
+            for (int s = 0; s < G; ++s) add4(acc, partial[(g + s) * LPG + lane]);
         }
     }
+    // Items split over work-groups: publish this share; the last share to
+    // arrive sums all shares in slot order.  Only the partials cross
+    // work-groups, so instead of a release/acquire pair (which writes back
+    // and invalidates the whole L2 of the XCD) they are written through to
+    // memory with system-scope stores, complete (vmcnt 0) before the
+    // share's arrival is counted, and read back with system-scope loads
+    // by the last share, after its count shows every other arrival.
+    bool lead = rec.item >= 0 && rec.lead;
+    if (task.n_split > 0) {
+        float *slot = a.split_partial + static_cast<size_t>(task.split_first + task.split_idx) * a.Kp + 4 * lane;
+        if (g == 0 && qlane) {
+            __hip_atomic_store(slot + 0, acc.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(slot + 1, acc.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(slot + 2, acc.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(slot + 3, acc.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the stores are complete
+        __syncthreads();
+        if (tid == 0) {
+            int32_t *cnt = a.split_count + task.split_first;
+            const int old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int last = old == task.n_split - 1;
+            if (last) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            is_last = last;
+        }
+        __syncthreads();
+        if (is_last) {
+            if (g == 0 && qlane) {
+                acc = zero;
+                const float *first = a.split_partial + static_cast<size_t>(task.split_first) * a.Kp + 4 * lane;
+                for (int s = 0; s < task.n_split; ++s) {
+                    const float *q = first + static_cast<size_t>(s) * a.Kp;
+                    acc.x += __hip_atomic_load(q + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    acc.y += __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    acc.z += __hip_atomic_load(q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    acc.w += __hip_atomic_load(q + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+        } else {
+            lead = false;
+        }
+    }
+
+    if (lead) item_update<LPG>(a, task.side, rec.item, st.x, acc, lane, qlane);
 }
 
 template <int LPG>

@@ -214,6 +214,36 @@ def test_checkpoint_resume_is_bit_identical():
     c.close()
 
 
+def test_tune_keeps_chain_and_is_reproducible():
+    """Tuning times candidate schedules on copies of the state: the chain is
+    unchanged, and a context given the chosen value directly steps to the
+    same bits.  Every candidate schedule stays within the parity bound."""
+    wl = CASES["gauss_K50_zipf"]()
+    a = pkg.PSGLD.from_workload(wl)
+    a.tune(wl.eps_a, candidates=(64,))
+    a.step(3, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    before = a.factors()
+    chosen = a.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(8, 64), iters=4)
+    assert chosen in (8, 64)
+    after = a.factors()
+    assert all(np.array_equal(x, y) for x, y in zip(before, after)) and a.iteration() == 3
+    a.step(5, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    b = pkg.PSGLD.from_workload(wl)   # loads with the value remembered for this shape
+    b.tune(wl.eps_a, candidates=(64,))
+    b.step(3, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    b.tune(wl.eps_a, candidates=(chosen,))
+    b.step(5, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    assert all(np.array_equal(x, y) for x, y in zip(a.factors(), b.factors()))
+    a.close()
+    b.close()
+    for L in (1, 8, 200):
+        s = pkg.PSGLD.from_workload(wl)
+        s.tune(wl.eps_a, candidates=(L,))
+        err, _ = step_parity(wl, 2, sampler=s)
+        s.close()
+        assert err <= TOL_FP32, (L, err)
+
+
 def test_nonfinite_is_reported():
     wl = CASES["K3_ragged_B7"]()
     s = pkg.PSGLD.from_workload(wl)
