@@ -33,6 +33,7 @@ import workloads  # noqa: E402
 
 METRIC = "observed-entry SGLD updates/s at matched held-out RMSE; served-job p50/p99"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 
 
 class HipEvents:
@@ -82,7 +83,33 @@ def algorithmic_bytes(wl, n_p, ho_p, t):
     return b
 
 
+def dense_part_cells(wl):
+    """Cells (all, masked or not) of each part's blocks: the dense kernels
+    stream every cell of a dense block."""
+    rp = np.bincount(pkg_pieces(wl, "row"), minlength=wl.B)
+    cp = np.bincount(pkg_pieces(wl, "col"), minlength=wl.B)
+    return np.array([sum(int(rp[b]) * int(cp[(b + p) % wl.B]) for b in range(wl.B)) for p in range(wl.B)])
+
+
+def dense_algorithmic(wl, cells_p, ho_p, t):
+    """(bytes, flops) of one dense iteration: every cell of the part's blocks
+    read once (FP32 value + mask byte), factors read and written once in
+    FP32, FP64 sums at kept iterations, FP64 held-out sums after burn-in; 6K
+    flops per cell for mu = W H, G_H = W^T E and G_W = E H^T."""
+    p = t % wl.B
+    b = 5 * cells_p[p] + 8 * (wl.I + wl.J) * wl.K
+    if t >= wl.burn_in:
+        b += 16 * ho_p[p]
+        if (t - wl.burn_in) % wl.thin == 0:
+            b += 32 * (wl.I + wl.J) * wl.K
+    return b, 6 * wl.K * cells_p[p]
+
+
 def make_workload(name):
+    if name == "dense_tweedie_1025x100k":
+        wl = workloads.dense_tweedie()
+        wl.thin = 10
+        return wl
     if name == "sparse_ratings_70k":
         wl = workloads.sparse_ratings()
         wl.thin = 10
@@ -118,6 +145,8 @@ def main():
     ap.add_argument("--workload", default="sparse_ratings_70k")
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
+                    help="operand precision of the dense-block kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,12 +161,18 @@ def main():
           f"({time.perf_counter() - t_gen:.1f} s to generate)", file=sys.stderr, flush=True)
 
     ev = HipEvents()
-    s = pkg.PSGLD.from_workload(wl)
+    dense = wl.dense is not None
+    prec = pkg.PSGLD_BF16_DENSE if args.precision == "bf16" else pkg.PSGLD_FP32
+    t_load = time.perf_counter()
+    s = pkg.PSGLD.from_workload(wl, dense=dense, precision=prec)
+    print(f"[bench] loaded in {time.perf_counter() - t_load:.1f} s", file=sys.stderr, flush=True)
     stream = s.stream()
-    t_tune = time.perf_counter()
-    chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
-    print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
-          file=sys.stderr, flush=True)
+    chosen = None
+    if not dense:
+        t_tune = time.perf_counter()
+        chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
+        print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
+              file=sys.stderr, flush=True)
     n_p, N = s.part_sizes()
     ho_part = (np.asarray(pkg_pieces(wl, "col"))[wl.hcol] - np.asarray(pkg_pieces(wl, "row"))[wl.hrow]) % wl.B
     ho_p = np.bincount(ho_part, minlength=wl.B)
@@ -174,11 +209,32 @@ def main():
     durs = np.array([ev.elapsed_ms(evs[2 * t], evs[2 * t + 1]) for t in range(args.steps)])
     s.sync()
     rmse2 = s.heldout_rmse() if args.steps > wl.burn_in else None
-    alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
     avg_ms = float(durs.mean())
-    achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
-    print(f"[bench] pass 2: kernel avg {avg_ms * 1e3:.2f} us, {achieved:.1f} GB/s algorithmic, "
-          f"RMSE {rmse2}", file=sys.stderr, flush=True)
+    if dense:
+        cells_p = dense_part_cells(wl)
+        bf = np.array([dense_algorithmic(wl, cells_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
+        alg, flops = bf[:, 0], bf[:, 1]
+        t_hbm = alg.mean() / (HBM_PEAK_GBS * 1e9)
+        t_mfma = flops.mean() / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
+        if t_mfma > t_hbm:
+            achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[args.precision],
+                    "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[args.precision]}
+        else:
+            achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS}
+        roof.update({"traffic": None, "kernel": "dense iteration (dense_tile_kernel + dense_w_update_kernel"
+                     " + dense_heldout_kernel)", "avg_launch_us": avg_ms * 1e3,
+                     "alg_bytes_per_launch": float(alg.mean()), "flops_per_launch": float(flops.mean())})
+    else:
+        alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
+        achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sparse_iter_kernel",
+                "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": float(alg.mean())}
+    print(f"[bench] pass 2: iteration avg {avg_ms * 1e3:.2f} us, roofline {roof['achieved']:.1f} "
+          f"{roof['unit']} ({roof['bound']}), RMSE {rmse2}", file=sys.stderr, flush=True)
     s.close()
 
     cpu = None
@@ -189,16 +245,15 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32" if dense and args.precision == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
                    "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
-                   "heldout_rmse": rmse, "entries_per_group": chosen, "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sparse_iter_kernel", "avg_launch_us": avg_ms * 1e3,
-                     "alg_bytes_per_launch": float(alg.mean())},
+                   "heldout_rmse": rmse, "entries_per_group": chosen, "dense": dense,
+                   "precision": args.precision if dense else "f32", "parallelism": "single-gpu"},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

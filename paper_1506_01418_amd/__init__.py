@@ -318,13 +318,20 @@ class PSGLD:
         self.n_heldout = 0
 
     @classmethod
-    def from_workload(cls, wl, **overrides):
+    def from_workload(cls, wl, dense=False, **overrides):
+        """Context for a workload; dense=True loads it with psgld_load_dense
+        (the workload's dense matrix and training mask)."""
         kw = dict(beta=wl.beta, phi=wl.phi, prior=wl.prior, lambda_w=wl.lambda_w,
                   lambda_h=wl.lambda_h, mirror=wl.mirror, seed=wl.seed, burn_in=wl.burn_in,
                   thin=wl.thin)
         kw.update(overrides)
         s = cls(wl.I, wl.J, wl.K, wl.B, **kw)
-        s.load_coo(wl.row, wl.col, wl.val)
+        if dense:
+            if wl.dense is None:
+                raise ValueError("workload has no dense matrix")
+            s.load_dense(wl.dense, wl.mask)
+        else:
+            s.load_coo(wl.row, wl.col, wl.val)
         if len(wl.hrow):
             s.load_heldout(wl.hrow, wl.hcol, wl.hval)
         s.set_factors(wl.W0, wl.H0)

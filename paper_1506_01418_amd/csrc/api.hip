@@ -37,6 +37,7 @@ namespace {
 thread_local std::string g_create_error;
 constexpr uint32_t kStateMagic = 0x50534744u;  // "PSGD"
 constexpr uint32_t kStateVersion = 1;
+constexpr int kDenseLLPerBlock = 16;   // work-groups per dense block in the log-likelihood
 
 bool is_gfx950(int device)
 {
@@ -90,6 +91,23 @@ struct psgld_ctx {
     bool ho_has_val = false;
     std::vector<int32_t> ho_part;
     std::vector<int64_t> part_visits;
+
+    // dense blocks (psgld_load_dense)
+    int64_t nnz_sparse = 0;                 // training entries stored as coordinates
+    std::vector<uint8_t> skip;              // skip[p * B + b]: block (b, (b+p) mod B) is dense
+    std::vector<int32_t> dblock_of;         // (b * B + c) -> index into dblocks_host, or -1
+    std::vector<DenseBlock> dblocks_host;   // part-major
+    std::vector<DenseTile> dtiles_host;     // part-major, a block's work-groups consecutive
+    std::vector<int64_t> dblock_first_tile; // index into dtiles_host of each block's first work-group
+    std::vector<int64_t> dblk_off, dblk_cnt, dtile_off, dtile_cnt;
+    std::vector<uint8_t> dmask_host;
+    DenseBlock *dblocks = nullptr;
+    DenseTile *dtiles = nullptr;
+    float *dval = nullptr;
+    uint8_t *dmask = nullptr;
+    float *w_partial = nullptr;
+    DenseHeld *dheld = nullptr;
+    int dense_max_m = 0, KS = 0;
 
     int32_t *nonfinite = nullptr;
     double *ll_partials = nullptr, *ll_out = nullptr;
@@ -192,7 +210,8 @@ psgld_status upload_schedule(psgld_ctx *c)
     for (int32_t p = 0; p < B; ++p) {
         PartSchedule ps;
         build_part_schedule(c->pre_r.data() + static_cast<size_t>(p) * I, c->pre_c.data() + static_cast<size_t>(p) * J,
-                            I, J, c->row_piece, c->col_piece, B, p, c->lpg, c->sched, ps);
+                            I, J, c->row_piece, c->col_piece, B, p, c->lpg, c->sched,
+                            c->skip.empty() ? nullptr : c->skip.data() + static_cast<size_t>(p) * B, ps);
         c->task_off[p] = static_cast<int64_t>(tasks.size());
         c->n_tasks[p] = static_cast<int64_t>(ps.tasks.size());
         tasks.insert(tasks.end(), ps.tasks.begin(), ps.tasks.end());
@@ -320,6 +339,7 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
     ec.resize(static_cast<size_t>(nnz) + kEntryPad, Entry{0, 0.f});
 
     c->N = nnz;
+    c->nnz_sparse = nnz;
     c->n_p.assign(B, 0);
     for (int32_t p = 0; p < B; ++p) c->n_p[p] = pre_r[static_cast<size_t>(p + 1) * I] - pre_r[static_cast<size_t>(p) * I];
 
@@ -355,6 +375,8 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
     c->loaded = true;
     return PSGLD_OK;
 }
+
+int32_t dense_slot_rows(const psgld_ctx *c) { return (c->dense_max_m + 31) / 32 * 32; }
 
 psgld_status check_values(psgld_ctx *c, int64_t n, const float *val)
 {
@@ -457,6 +479,49 @@ psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule 
     a.ho_sum = c->ho_sum;
     a.nonfinite = c->nonfinite;
     HIPTRY(c, launch_sparse_iter(a, c->lik_kind, c->lpg, c->stream));
+    if (!c->dblocks_host.empty() && c->dblk_cnt[p] > 0) {
+        DenseIterArgs d{};
+        d.x_old[0] = a.x_old[0];
+        d.x_old[1] = a.x_old[1];
+        d.x_new[0] = a.x_new[0];
+        d.x_new[1] = a.x_new[1];
+        d.blocks = c->dblocks + c->dblk_off[p];
+        d.n_blocks = static_cast<int32_t>(c->dblk_cnt[p]);
+        d.tiles = c->dtiles + c->dtile_off[p];
+        d.n_tiles = static_cast<int32_t>(c->dtile_cnt[p]);
+        d.val = c->dval;
+        d.mask = c->dmask;
+        d.w_partial = c->w_partial;
+        d.slot_rows = dense_slot_rows(c);
+        d.row_align = c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16;
+        d.K = c->K;
+        d.Kp = c->Kp;
+        d.KS = c->KS;
+        d.eps = a.eps;
+        d.sigma = a.sigma;
+        d.scale = a.scale;
+        d.lambda[0] = a.lambda[0];
+        d.lambda[1] = a.lambda[1];
+        d.inv_phi = a.inv_phi;
+        d.beta = a.beta;
+        d.mu_floor = a.mu_floor;
+        d.seed_lo = a.seed_lo;
+        d.seed_hi = a.seed_hi;
+        d.t = a.t;
+        d.mirror = a.mirror;
+        d.prior_kind = a.prior_kind;
+        d.flags = a.flags;
+        d.do_moments = a.do_moments;
+        for (int side = 0; side < 2; ++side) {
+            d.sum[side] = a.sum[side];
+            d.sum2[side] = a.sum2[side];
+        }
+        d.do_heldout = a.do_heldout && c->dheld != nullptr;
+        d.heldout = c->dheld;
+        d.ho_sum = c->ho_sum;
+        d.nonfinite = c->nonfinite;
+        HIPTRY(c, launch_dense_iter(d, c->lik_kind, c->opt.precision == PSGLD_BF16_DENSE, c->dense_max_m, c->stream));
+    }
     if (a.do_moments) c->n_kept++;
     if (a.do_heldout) c->part_visits[p]++;
     c->cur ^= 1;
@@ -537,7 +602,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     c->lik = *lik;
     c->prior = *prior;
     c->opt = o;
-    c->lik_kind = lik->beta == 2.0 ? LIK_GAUSS : (lik->beta == 1.0 ? LIK_POISSON : LIK_GENERAL);
+    c->lik_kind = lik_kind_of(lik->beta);
     // partitions P_B([I]), P_B([J]): given, or contiguous with the first (n mod B) pieces longer
     for (int side = 0; side < 2; ++side) {
         const int64_t n = side == 0 ? I : J;
@@ -593,17 +658,128 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
     c->err.clear();
     if (c->loaded) return c->fail(PSGLD_E_STATE, "data already loaded");
     if (!V) return c->fail(PSGLD_E_ARG, "V is required");
+    const int64_t I = c->I, J = c->J;
+    const int32_t B = c->B;
+    for (int64_t i = 0; i < I; ++i)
+        for (int64_t j = 0; j < J; ++j) {
+            const size_t m = static_cast<size_t>(i) * J + j;
+            if (mask && !mask[m]) continue;
+            psgld_status s = check_values(c, 1, V + m);
+            if (s) return c->fail(s, c->err + " (cell " + std::to_string(i) + ", " + std::to_string(j) + ")");
+        }
+    // Dense blocks need contiguous pieces, at most kDenseMaxRows rows, rank at
+    // most kDenseMaxK, and a training density above the threshold.
+    const bool contiguous = std::is_sorted(c->row_piece.begin(), c->row_piece.end()) &&
+                            std::is_sorted(c->col_piece.begin(), c->col_piece.end());
+    std::vector<int64_t> r0(B + 1, 0), c0(B + 1, 0);
+    for (int64_t i = 0; i < I; ++i) r0[c->row_piece[i] + 1]++;
+    for (int64_t j = 0; j < J; ++j) c0[c->col_piece[j] + 1]++;
+    for (int32_t b = 0; b < B; ++b) {
+        r0[b + 1] += r0[b];
+        c0[b + 1] += c0[b];
+    }
+    std::vector<uint8_t> dense(static_cast<size_t>(B) * B, 0);
+    std::vector<int64_t> train(static_cast<size_t>(B) * B, 0);
+    if (contiguous && c->K <= kDenseMaxK) {
+        for (int32_t b = 0; b < B; ++b)
+            for (int32_t cc = 0; cc < B; ++cc) {
+                const int64_t m = r0[b + 1] - r0[b], nn = c0[cc + 1] - c0[cc];
+                int64_t cnt = 0;
+                for (int64_t i = r0[b]; i < r0[b + 1]; ++i)
+                    for (int64_t j = c0[cc]; j < c0[cc + 1]; ++j) cnt += mask ? (mask[i * J + j] != 0) : 1;
+                train[static_cast<size_t>(b) * B + cc] = cnt;
+                dense[static_cast<size_t>(b) * B + cc] =
+                    m <= kDenseMaxRows && cnt > c->opt.dense_threshold * static_cast<double>(m * nn);
+            }
+    }
+    // coordinates of the sparse blocks
     std::vector<int32_t> row, col;
     std::vector<float> val;
-    for (int64_t i = 0; i < c->I; ++i)
-        for (int64_t j = 0; j < c->J; ++j) {
-            const size_t m = static_cast<size_t>(i) * c->J + j;
+    for (int64_t i = 0; i < I; ++i)
+        for (int64_t j = 0; j < J; ++j) {
+            const size_t m = static_cast<size_t>(i) * J + j;
             if (mask && !mask[m]) continue;
+            if (dense[static_cast<size_t>(c->row_piece[i]) * B + c->col_piece[j]]) continue;
             row.push_back(static_cast<int32_t>(i));
             col.push_back(static_cast<int32_t>(j));
             val.push_back(V[m]);
         }
-    return psgld_load_coo(c, static_cast<int64_t>(row.size()), row.data(), col.data(), val.data());
+    c->skip.assign(static_cast<size_t>(B) * B, 0);
+    for (int32_t p = 0; p < B; ++p)
+        for (int32_t b = 0; b < B; ++b) c->skip[static_cast<size_t>(p) * B + b] = dense[static_cast<size_t>(b) * B + (b + p) % B];
+    psgld_status s;
+    if ((s = ensure_device(c))) return s;
+    if ((s = build_layout(c, static_cast<int64_t>(row.size()), row.data(), col.data(), val.data()))) return s;
+
+    // dense storage, part-major: values, mask, block table, tiles
+    std::vector<float> dv;
+    std::vector<DenseTile> tiles;
+    c->dblock_of.assign(static_cast<size_t>(B) * B, -1);
+    c->dblocks_host.clear();
+    c->dblock_first_tile.clear();
+    c->dmask_host.clear();
+    c->dblk_off.assign(B, 0);
+    c->dblk_cnt.assign(B, 0);
+    c->dtile_off.assign(B, 0);
+    c->dtile_cnt.assign(B, 0);
+    int64_t max_partial_slots = 0;
+    c->dense_max_m = 0;
+    for (int32_t p = 0; p < B; ++p) {
+        c->dblk_off[p] = static_cast<int64_t>(c->dblocks_host.size());
+        c->dtile_off[p] = static_cast<int64_t>(tiles.size());
+        int32_t partial = 0;
+        for (int32_t b = 0; b < B; ++b) {
+            const int32_t cc = (b + p) % B;
+            if (!dense[static_cast<size_t>(b) * B + cc]) continue;
+            DenseBlock blk;
+            blk.row0 = static_cast<int32_t>(r0[b]);
+            blk.m = static_cast<int32_t>(r0[b + 1] - r0[b]);
+            blk.col0 = static_cast<int32_t>(c0[cc]);
+            blk.n = static_cast<int32_t>(c0[cc + 1] - c0[cc]);
+            blk.v_off = static_cast<int64_t>(dv.size());
+            blk.first_partial = partial;
+            const int32_t wg_cols = kDenseTileCols * kDenseSubTiles;
+            blk.n_tiles = (blk.n + wg_cols - 1) / wg_cols;
+            const int32_t idx_in_part = static_cast<int32_t>(c->dblocks_host.size() - c->dblk_off[p]);
+            for (int32_t tt = 0; tt < blk.n_tiles; ++tt)
+                tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, 0, 0, {0, 0, 0}});
+            partial += blk.n_tiles;
+            for (int64_t i = 0; i < blk.m; ++i)
+                for (int64_t j = 0; j < blk.n; ++j) {
+                    const size_t m = static_cast<size_t>(blk.row0 + i) * J + blk.col0 + j;
+                    const uint8_t t = mask ? (mask[m] != 0) : 1;
+                    dv.push_back(t ? V[m] : 0.f);
+                    c->dmask_host.push_back(t);
+                }
+            c->dense_max_m = std::max(c->dense_max_m, blk.m);
+            c->dblock_first_tile.push_back(static_cast<int64_t>(tiles.size()) - blk.n_tiles);
+            c->dblock_of[static_cast<size_t>(b) * B + cc] = static_cast<int32_t>(c->dblocks_host.size());
+            c->dblocks_host.push_back(blk);
+            c->N += train[static_cast<size_t>(b) * B + cc];
+            c->n_p[p] += train[static_cast<size_t>(b) * B + cc];
+        }
+        c->dblk_cnt[p] = static_cast<int64_t>(c->dblocks_host.size()) - c->dblk_off[p];
+        c->dtile_cnt[p] = static_cast<int64_t>(tiles.size()) - c->dtile_off[p];
+        max_partial_slots = std::max<int64_t>(max_partial_slots, partial);
+    }
+    if (!c->dblocks_host.empty()) {
+        const int align = c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16;
+        c->KS = (c->K + align - 1) / align * align;
+        HIPTRY(c, dense_prepare(c->dense_max_m, c->KS));
+        if ((s = upload(c, &c->dblocks, c->dblocks_host))) return s;
+        if ((s = upload(c, &c->dtiles, tiles))) return s;
+        c->dtiles_host = tiles;
+        if ((s = upload(c, &c->dval, dv))) return s;
+        if ((s = upload(c, &c->dmask, c->dmask_host))) return s;
+        // one slot per tile, each as tall as the tallest padded block
+        if ((s = dev_alloc(c, &c->w_partial, static_cast<size_t>(max_partial_slots) * dense_slot_rows(c) * c->Kp)))
+            return s;
+        // the log-likelihood reduction also covers the dense blocks
+        dev_free(c, c->ll_partials);
+        c->ll_partials = nullptr;
+        if ((s = dev_alloc(c, &c->ll_partials, c->ll_blocks + c->dblocks_host.size() * kDenseLLPerBlock))) return s;
+    }
+    return PSGLD_OK;
 }
 
 psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
@@ -625,8 +801,28 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     const int32_t B = c->B;
     std::vector<int32_t> pre(static_cast<size_t>(B) * I + 1, 0);
     c->ho_part.resize(n);
+    // cells inside dense blocks are summed by the dense kernel's work-group
+    // that covers them
+    std::vector<uint8_t> in_dense(n, 0);
+    std::vector<std::vector<DenseHeld>> dh(c->dtiles_host.size());
+    std::vector<uint8_t> dmask_dev;
+    if (!c->dblocks_host.empty()) dmask_dev = c->dmask_host;
+    const int32_t wg_cols = kDenseTileCols * kDenseSubTiles;
     for (int64_t e = 0; e < n; ++e) {
         c->ho_part[e] = part_of(c, row[e], col[e]);
+        const int32_t db = c->dblock_of.empty() ? -1
+                                                : c->dblock_of[static_cast<size_t>(c->row_piece[row[e]]) * B + c->col_piece[col[e]]];
+        if (db >= 0) {
+            const DenseBlock &blk = c->dblocks_host[db];
+            const int32_t i = row[e] - blk.row0, j = col[e] - blk.col0;
+            const size_t cell = static_cast<size_t>(blk.v_off) + static_cast<size_t>(i) * blk.n + j;
+            if (c->dmask_host[cell] == kMaskTrain) return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
+            if (dmask_dev[cell] == kMaskHeld) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
+            dmask_dev[cell] = kMaskHeld;
+            in_dense[e] = 1;
+            dh[c->dblock_first_tile[db] + j / wg_cols].push_back(DenseHeld{i, j % wg_cols, static_cast<int32_t>(e), 0});
+            continue;
+        }
         pre[static_cast<size_t>(c->ho_part[e]) * I + row[e] + 1]++;
     }
     for (size_t k = 1; k < pre.size(); ++k) pre[k] += pre[k - 1];
@@ -634,14 +830,31 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     {
         std::vector<int32_t> fill(pre.begin(), pre.end() - 1);
         for (int64_t e = 0; e < n; ++e)
-            he[fill[static_cast<size_t>(c->ho_part[e]) * I + row[e]]++] =
-                HeldEntry{col[e] * c->Kp, static_cast<int32_t>(e)};
+            if (!in_dense[e])
+                he[fill[static_cast<size_t>(c->ho_part[e]) * I + row[e]]++] =
+                    HeldEntry{col[e] * c->Kp, static_cast<int32_t>(e)};
+        he.resize(pre.back());
     }
-    // distinct cells, disjoint from the training entries
+    // dense-block cells, grouped by work-group, each group in column order
+    std::vector<DenseHeld> dflat;
+    for (size_t w = 0; w < dh.size(); ++w) {
+        std::sort(dh[w].begin(), dh[w].end(), [](const DenseHeld &a, const DenseHeld &b) {
+            return a.col != b.col ? a.col < b.col : a.row < b.row;
+        });
+        c->dtiles_host[w].ho_begin = static_cast<int32_t>(dflat.size());
+        dflat.insert(dflat.end(), dh[w].begin(), dh[w].end());
+        c->dtiles_host[w].ho_end = static_cast<int32_t>(dflat.size());
+    }
+    if (!c->dblocks_host.empty()) {
+        HIPTRY(c, hipMemcpy(c->dtiles, c->dtiles_host.data(), c->dtiles_host.size() * sizeof(DenseTile),
+                            hipMemcpyHostToDevice));
+        HIPTRY(c, hipMemcpy(c->dmask, dmask_dev.data(), dmask_dev.size(), hipMemcpyHostToDevice));
+    }
+    // coordinate-block cells: distinct, and disjoint from the training entries
     std::vector<int32_t> rp(static_cast<size_t>(B) * I + 1);
     HIPTRY(c, hipMemcpy(rp.data(), c->rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    std::vector<Entry> er(static_cast<size_t>(c->N));
-    if (c->N) HIPTRY(c, hipMemcpy(er.data(), c->ent_r, er.size() * sizeof(Entry), hipMemcpyDeviceToHost));
+    std::vector<Entry> er(static_cast<size_t>(c->nnz_sparse));
+    if (c->nnz_sparse) HIPTRY(c, hipMemcpy(er.data(), c->ent_r, er.size() * sizeof(Entry), hipMemcpyDeviceToHost));
     for (size_t k = 0; k + 1 < pre.size(); ++k) {
         std::sort(he.begin() + pre[k], he.begin() + pre[k + 1],
                   [](const HeldEntry &a, const HeldEntry &b) { return a.off < b.off; });
@@ -655,6 +868,7 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     }
     if ((s = upload(c, &c->ho_ptr, pre))) return s;
     if ((s = upload(c, &c->ho_ent, he))) return s;
+    if ((s = upload(c, &c->dheld, dflat))) return s;
     if ((s = dev_alloc(c, &c->ho_sum, static_cast<size_t>(n)))) return s;
     HIPTRY(c, hipMemset(c->ho_sum, 0, std::max<int64_t>(n, 1) * sizeof(double)));
     c->n_ho = n;
@@ -880,9 +1094,13 @@ psgld_status psgld_log_likelihood(psgld_ctx *c, double *ll)
     if (!ll) return c->fail(PSGLD_E_ARG, "ll is required");
     if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
     HIPTRY(c, hipSetDevice(c->opt.device));
-    HIPTRY(c, launch_loglik(c->W[c->cur], c->H[c->cur], c->row_of_entry, c->ent_r, c->N, c->K, c->Kp,
-                            c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials, c->ll_blocks,
-                            c->ll_out, c->stream));
+    HIPTRY(c, launch_loglik(c->W[c->cur], c->H[c->cur], c->row_of_entry, c->ent_r, c->nnz_sparse, c->K, c->Kp,
+                            c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials, c->ll_blocks, c->stream));
+    const int nd = static_cast<int>(c->dblocks_host.size());
+    HIPTRY(c, launch_dense_loglik(c->W[c->cur], c->H[c->cur], c->dblocks, nd, c->dval, c->dmask, c->K, c->Kp,
+                                  c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials + c->ll_blocks,
+                                  kDenseLLPerBlock, c->stream));
+    HIPTRY(c, launch_sum_in_order(c->ll_partials, c->ll_blocks + nd * kDenseLLPerBlock, c->ll_out, c->stream));
     psgld_status s = sync_and_check(c);
     if (s) return s;
     HIPTRY(c, hipMemcpy(ll, c->ll_out, sizeof(double), hipMemcpyDeviceToHost));

@@ -1,0 +1,326 @@
+// One PSGLD iteration over the dense blocks of a part, on the matrix cores.
+//
+// For a dense block (rows R_b, columns C_c) of the part, Eq. (8)-(9) need
+//   mu  = W_b H_c                (the block's means, Eq. (13))
+//   E   = mask * (V - mu~) mu~^(beta-2) / phi
+//   G_H = W_b^T E                (K x |C_c|: complete per column)
+//   G_W = E H_c^T                (|R_b| x K: summed over the block's columns)
+// A work-group owns up to kDenseSubTiles x 64 columns of one block and all
+// of its m <= 128 rows.  The three products run on MFMA 16x16 tiles (FP32
+// operands, or BF16 operands rounded to nearest even, always FP32
+// accumulation) from LDS copies of W_b, a 64-column sub-tile of H and E,
+// with four independent accumulators per wave.  The H columns are updated
+// straight from the G_H accumulators -- each lane holds four consecutive k
+// of one column, which is exactly one Philox quad.  G_W accumulates over
+// the work-group's sub-tiles and is left as its partial, which
+// dense_w_update_kernel sums over the block's work-groups in order before
+// updating the block's W rows.
+#include "internal.hpp"
+#include "noise.hpp"
+
+namespace psgld {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kDenseThreads = 256;   // 4 waves
+constexpr int kNT = kDenseTileCols;
+
+// D_t(16x16) += A(16 x kd) B_t(kd x 16) for t < nb (at most NACC), all with
+// the same A rows: A(r, k) = fa(r, k), B_t(k, c) = fb(t, k, c).  FP32:
+// 16x16x4 steps (kd a multiple of 4); BF16: 16x16x32 steps (kd a multiple
+// of 32), operands rounded to nearest even.  Lane layouts (checked on the
+// device): A lane l holds row l%16 and k-slice l/16; B lane l holds column
+// l%16; D lane l, register r holds (4 (l/16) + r, l%16).
+template <bool BF16, int NACC, typename FA, typename FB>
+__device__ __forceinline__ void mma16(v4f (&acc)[NACC], int nb, int kd, int lane, FA fa, FB fb)
+{
+    const int r = lane & 15, h = lane >> 4;
+    if constexpr (BF16) {
+        for (int k = 0; k < kd; k += 32) {
+            v8bf av;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) av[v] = static_cast<__bf16>(fa(r, k + 8 * h + v));
+#pragma unroll
+            for (int t = 0; t < NACC; ++t) {
+                if (t >= nb) break;
+                v8bf bv;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) bv[v] = static_cast<__bf16>(fb(t, k + 8 * h + v, r));
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    } else {
+#pragma unroll 2
+        for (int k = 0; k < kd; k += 4) {
+            const float av = fa(r, k + h);
+#pragma unroll
+            for (int t = 0; t < NACC; ++t) {
+                if (t >= nb) break;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb(t, k + h, r), acc[t], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// The Langevin step of four consecutive parameters k0..k0+3 of row `index`
+// of factor `side`, with gradient g of the scaled likelihood.
+__device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, int side, int index, int k0, const float xo[4],
+                               const float g[4])
+{
+    const bool frozen = (a.flags & (side == 0 ? PSGLD_TEST_FREEZE_W : PSGLD_TEST_FREEZE_H)) != 0;
+    const bool noisy = !frozen && !(a.flags & PSGLD_TEST_NOISE_OFF);
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (noisy) {
+        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, a.t, static_cast<uint32_t>(side),
+                                   static_cast<uint32_t>(index), static_cast<uint32_t>(k0 / 4));
+        z[0] = nz.z[0];
+        z[1] = nz.z[1];
+        z[2] = nz.z[2];
+        z[3] = nz.z[3];
+    }
+    const float lam = a.lambda[side];
+    float xn[4];
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float v = xo[c];
+        if (!frozen) {
+            const float pg = a.prior_kind == PSGLD_PRIOR_EXPONENTIAL ? (xo[c] >= 0.f ? -lam : lam) : -lam * xo[c];
+            v = xo[c] + a.eps * (a.scale * g[c] + pg) + a.sigma * z[c];
+            if (a.mirror) v = fabsf(v);
+        }
+        if (k0 + c >= a.K) v = 0.f;
+        finite = finite && isfinite(v);
+        xn[c] = v;
+    }
+    const size_t off = static_cast<size_t>(index) * a.Kp + k0;
+    *reinterpret_cast<float4 *>(a.x_new[side] + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+    if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(a.t));
+    if (a.do_moments) {
+        double *s = a.sum[side] + off;
+        double *s2 = a.sum2[side] + off;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s[c] += static_cast<double>(xn[c]);
+            s2[c] += static_cast<double>(xn[c]) * static_cast<double>(xn[c]);
+        }
+    }
+}
+
+// One work-group: up to kDenseSubTiles consecutive 64-column sub-tiles of
+// one block.  Wave w takes 16-row tiles w, w+4, ... of each product; the
+// products over the rank (G_H and G_W) use one 16-row k-tile per wave
+// (K <= 64).  G_W accumulates in registers over the sub-tiles and is
+// written once, as this work-group's partial.
+template <bool BF16, int LIK>
+__global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs a)
+{
+    extern __shared__ float lds[];
+    const DenseTile tile = a.tiles[blockIdx.x];
+    const DenseBlock blk = a.blocks[tile.block];
+    const int m = blk.m, MT = (m + a.row_align - 1) / a.row_align * a.row_align;
+    const int KS = a.KS, Kp = a.Kp;
+    const int sw = KS + 1;            // odd row strides: no LDS bank conflicts
+    const int se = kNT + 1;
+    float *sW = lds;                   // [MT][KS+1]   W_b
+    float *sH = sW + MT * sw;          // [NT][KS+1]   H columns of the sub-tile
+    float *sE = sH + kNT * sw;         // [MT][NT+1]   E
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c16 = lane & 15, h4 = lane >> 4;
+    const float *Wold = a.x_old[0], *Hold = a.x_old[1];
+
+    for (int i = wave; i < MT; i += kDenseThreads / 64)
+        for (int k = lane; k < KS; k += 64)
+            sW[i * sw + k] = (i < m && k < Kp) ? Wold[static_cast<size_t>(blk.row0 + i) * Kp + k] : 0.f;
+
+    const float *V = a.val + blk.v_off;
+    const uint8_t *M = a.mask + blk.v_off;
+    const int kt = wave;                          // this wave's k-tile in G_H and G_W
+    const bool has_kt = kt * 16 < KS;
+    const int n_it = MT / 16;                     // 16-row tiles of the block
+    v4f gw[kDenseMaxRows / 16];
+#pragma unroll
+    for (int t = 0; t < kDenseMaxRows / 16; ++t) gw[t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int sub = 0; sub < kDenseSubTiles; ++sub) {
+        const int cl = tile.col + sub * kNT;      // first column of the sub-tile, in the block
+        if (cl >= blk.n) break;
+        const int ncol = min(kNT, blk.n - cl);
+        const int col0 = blk.col0 + cl;
+        __syncthreads();                          // previous sub-tile done with sH, sE
+        for (int j = wave; j < kNT; j += kDenseThreads / 64)
+            for (int k = lane; k < KS; k += 64)
+                sH[j * sw + k] = (j < ncol && k < Kp) ? Hold[static_cast<size_t>(col0 + j) * Kp + k] : 0.f;
+        __syncthreads();
+
+        // mu = W_b H^T (MT x 64) and E
+        for (int it = wave; it < n_it; it += kDenseThreads / 64) {
+            v4f acc[4] = {};
+            mma16<BF16, 4>(acc, 4, KS, lane, [&](int r, int k) { return sW[(it * 16 + r) * sw + k]; },
+                           [&](int t, int k, int c) { return sH[(t * 16 + c) * sw + k]; });
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = t * 16 + c16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = it * 16 + 4 * h4 + r;
+                    // E for training cells; the mean itself for held-out cells
+                    // (read out and cleared below, before the products use E)
+                    float e = 0.f;
+                    if (i < m && j < ncol) {
+                        const size_t cell = static_cast<size_t>(i) * blk.n + cl + j;
+                        const uint8_t mk = M[cell];
+                        if (mk == kMaskTrain)
+                            e = tweedie_residual<LIK>(V[cell], acc[t][r], a.inv_phi, a.beta, a.mu_floor);
+                        else if (mk == kMaskHeld && a.do_heldout)
+                            e = acc[t][r];
+                    }
+                    sE[i * se + j] = e;
+                }
+            }
+        }
+        __syncthreads();
+        if (a.do_heldout && tile.ho_end > tile.ho_begin) {
+            // held-out cells of this sub-tile: add their mean, then zero them in E
+            for (int h = tile.ho_begin + tid; h < tile.ho_end; h += kDenseThreads) {
+                const DenseHeld c = a.heldout[h];
+                const int j = c.col - sub * kNT;
+                if (j < 0 || j >= kNT) continue;
+                a.ho_sum[c.slot] += static_cast<double>(sE[c.row * se + j]);
+                sE[c.row * se + j] = 0.f;
+            }
+            __syncthreads();
+        }
+
+        if (has_kt) {
+            // G_H = W_b^T E (k-tile kt x 64 columns): update the sub-tile's H columns
+            v4f acc[4] = {};
+            mma16<BF16, 4>(acc, 4, MT, lane, [&](int r, int i) { return sW[i * sw + kt * 16 + r]; },
+                           [&](int t, int i, int c) { return sE[i * se + t * 16 + c]; });
+            const int k0 = kt * 16 + 4 * h4;      // four consecutive k: one Philox quad
+            if (k0 < Kp) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int j = t * 16 + c16;
+                    if (j >= ncol) continue;
+                    const float g[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+                    const float xo[4] = {sH[j * sw + k0], sH[j * sw + k0 + 1], sH[j * sw + k0 + 2],
+                                         sH[j * sw + k0 + 3]};
+                    dense_langevin(a, 1, col0 + j, k0, xo, g);
+                }
+            }
+            // G_W^T += H^T E^T (k-tile kt x MT rows)
+            mma16<BF16, kDenseMaxRows / 16>(gw, n_it, kNT, lane,
+                                            [&](int r, int j) { return sH[j * sw + kt * 16 + r]; },
+                                            [&](int t, int j, int c) { return sE[(t * 16 + c) * se + j]; });
+        }
+    }
+
+    // this work-group's partial of G_W for the block's rows
+    if (has_kt) {
+        const int k0 = kt * 16 + 4 * h4;
+        if (k0 < Kp) {
+            float *part = a.w_partial + static_cast<size_t>(tile.partial) * a.slot_rows * Kp;
+#pragma unroll
+            for (int t = 0; t < kDenseMaxRows / 16; ++t) {
+                if (t >= n_it) break;
+                const int i = t * 16 + c16;
+                *reinterpret_cast<float4 *>(part + static_cast<size_t>(i) * Kp + k0) =
+                    make_float4(gw[t][0], gw[t][1], gw[t][2], gw[t][3]);
+            }
+        }
+    }
+}
+
+// W rows of the part's dense blocks: sum the tiles' partials in tile order,
+// then the Langevin step.  One thread per (row, quad).
+__global__ void dense_w_update_kernel(DenseIterArgs a)
+{
+    const int b = blockIdx.y;
+    const DenseBlock blk = a.blocks[b];
+    const int nq = a.Kp / 4;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= blk.m * nq) return;
+    const int i = w / nq, k0 = 4 * (w % nq);
+    // partials loaded eight at a time, added in partial order
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float *base = a.w_partial + (static_cast<size_t>(blk.first_partial) * a.slot_rows + i) * a.Kp + k0;
+    const size_t stride = static_cast<size_t>(a.slot_rows) * a.Kp;
+    for (int t0 = 0; t0 < blk.n_tiles; t0 += 8) {
+        float4 p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u < blk.n_tiles) p[u] = *reinterpret_cast<const float4 *>(base + (t0 + u) * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (t0 + u >= blk.n_tiles) break;
+            g.x += p[u].x;
+            g.y += p[u].y;
+            g.z += p[u].z;
+            g.w += p[u].w;
+        }
+    }
+    const float *x = a.x_old[0] + static_cast<size_t>(blk.row0 + i) * a.Kp + k0;
+    const float xo[4] = {x[0], x[1], x[2], x[3]};
+    const float gr[4] = {g.x, g.y, g.z, g.w};
+    dense_langevin(a, 0, blk.row0 + i, k0, xo, gr);
+}
+
+template <bool BF16>
+hipError_t launch_tiles(const DenseIterArgs &a, int lik, size_t lds, hipStream_t stream)
+{
+    const dim3 grid(static_cast<unsigned>(a.n_tiles)), block(kDenseThreads);
+    switch (lik) {
+    case LIK_GAUSS: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAUSS>), grid, block, lds, stream, a); break;
+    case LIK_POISSON: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_POISSON>), grid, block, lds, stream, a); break;
+    case LIK_HALF: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_HALF>), grid, block, lds, stream, a); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAMMA>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GENERAL>), grid, block, lds, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t dense_lds_bytes(int max_m, int KS)
+{
+    const int MT = (max_m + 31) / 32 * 32;   // at least the padded height of any block
+    return sizeof(float) * (static_cast<size_t>(MT) * (KS + 1) + static_cast<size_t>(kNT) * (KS + 1) +
+                            static_cast<size_t>(MT) * (kNT + 1));
+}
+
+hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max_m, hipStream_t stream)
+{
+    if (a.n_tiles == 0) return hipSuccess;
+    const size_t lds = dense_lds_bytes(max_m, a.KS);
+    hipError_t e = bf16 ? launch_tiles<true>(a, lik, lds, stream) : launch_tiles<false>(a, lik, lds, stream);
+    if (e != hipSuccess) return e;
+    const int rows_q = max_m * (a.Kp / 4);
+    hipLaunchKernelGGL(dense_w_update_kernel, dim3((rows_q + 127) / 128, a.n_blocks), dim3(128), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t dense_prepare(int max_m, int KS)
+{
+    const int lds = static_cast<int>(dense_lds_bytes(max_m, KS));
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAUSS>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_POISSON>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_HALF>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAMMA>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GENERAL>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAUSS>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_POISSON>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_HALF>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAMMA>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GENERAL>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace psgld

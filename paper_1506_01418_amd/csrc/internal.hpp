@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "model.hpp"
 #include "psgld.h"
 
 namespace psgld {
@@ -53,7 +54,6 @@ struct GroupRec {
     int32_t lead;   // 1 if this group applies the item's update
 };
 
-enum Lik : int { LIK_GAUSS = 0, LIK_POISSON = 1, LIK_GENERAL = 2 };
 
 // Arguments of one sparse iteration (one part), passed by value.
 struct SparseIterArgs {
@@ -95,6 +95,7 @@ struct ScheduleParams {
     bool xcd_remap = true;        // place each block's work on one XCD
 };
 
+
 // Host-side schedule of one part: work-group tasks and group records.
 struct PartSchedule {
     std::vector<WgTask> tasks;
@@ -102,20 +103,97 @@ struct PartSchedule {
     int32_t n_splits = 0;   // scratch slots used
 };
 // pre: offsets of the part's entries per row (length I+1) and per column
-// (length J+1); pieces of rows / columns; the part index p.
+// (length J+1); pieces of rows / columns; the part index p; skip_block[b]
+// (may be NULL) marks part blocks b handled elsewhere (dense blocks).
 void build_part_schedule(const int32_t *pre_r, const int32_t *pre_c, int64_t I, int64_t J,
                          const std::vector<int32_t> &row_piece, const std::vector<int32_t> &col_piece,
                          int32_t B, int32_t p, int lanes_per_group, const ScheduleParams &prm,
-                         PartSchedule &out);
+                         const uint8_t *skip_block, PartSchedule &out);
+
+// ---- dense blocks --------------------------------------------------------
+constexpr int kDenseTileCols = 64;   // columns of one MFMA sub-tile
+constexpr int kDenseSubTiles = 4;    // sub-tiles (consecutive) per work-group
+constexpr int kDenseMaxRows = 128;   // dense blocks have at most this many rows
+constexpr int kDenseMaxK = 64;       // and rank at most this
+
+// A dense block of a part: rows [row0, row0 + m), columns [col0, col0 + n);
+// its values and training mask are stored row-major (row stride n) at v_off;
+// its tiles' W partials occupy slots first_partial .. + n_tiles.
+struct DenseBlock {
+    int32_t row0, m, col0, n;
+    int64_t v_off;
+    int32_t first_partial, n_tiles;
+};
+
+// One work-group's share of a block: columns [col, col + kDenseSubTiles * 64)
+// of part block `block`; its W partial goes to slot `partial`; its held-out
+// cells are heldout[ho_begin .. ho_end) (in column order).
+struct DenseTile {
+    int32_t block;
+    int32_t col;
+    int32_t partial;
+    int32_t ho_begin, ho_end;
+    int32_t pad[3];
+};
+
+// Dense-block mask byte: 0 missing, 1 training cell, 2 held-out cell.
+constexpr uint8_t kMaskTrain = 1;
+constexpr uint8_t kMaskHeld = 2;
+
+// A held-out cell inside a dense block, listed with the work-group that
+// covers it: row in the block, column relative to the work-group's first
+// column, and output slot.
+struct DenseHeld {
+    int32_t row, col, slot, pad;
+};
+
+struct DenseIterArgs {
+    const float *x_old[2];
+    float *x_new[2];
+    const DenseBlock *blocks;   // the part's dense blocks
+    int32_t n_blocks;
+    const DenseTile *tiles;     // the part's tiles
+    int32_t n_tiles;
+    const float *val;
+    const uint8_t *mask;
+    float *w_partial;           // slot_rows x Kp floats per tile
+    int32_t slot_rows;          // rows of every W partial slot (the largest padded block height)
+    int32_t row_align;          // block heights are padded to this (16 FP32, 32 BF16)
+    int32_t K, Kp, KS;          // KS = K rounded up to row_align
+    float eps, sigma, scale;
+    float lambda[2];
+    float inv_phi, beta, mu_floor;
+    uint32_t seed_lo, seed_hi, t;
+    int32_t mirror, prior_kind;
+    uint32_t flags;
+    int32_t do_moments;
+    double *sum[2], *sum2[2];
+    int32_t do_heldout;
+    const DenseHeld *heldout;   // held-out cells of dense blocks, grouped by tile
+    double *ho_sum;
+    int32_t *nonfinite;
+};
+
+// Enqueues the dense work of one iteration (tiles with their held-out
+// sums, then the W rows).
+hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max_m, hipStream_t stream);
+// Raises the dynamic LDS limit of the tile kernels for blocks of max_m rows.
+hipError_t dense_prepare(int max_m, int KS);
+size_t dense_lds_bytes(int max_m, int KS);
+// FP64 log-likelihood partials of all dense blocks' training cells.
+hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
+                               const float *val, const uint8_t *mask, int K, int Kp, double beta, double phi,
+                               double mu_floor, double *partials, int per_block, hipStream_t stream);
 
 hipError_t launch_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                 hipStream_t stream);
 hipError_t launch_normals(int64_t n, uint64_t seed, const int64_t *t, const uint32_t *stream_id,
                           const int64_t *index, int K, float *z, float *radius, hipStream_t stream);
-// FP64 training log-likelihood over all parts' row-sorted entries.
+// FP64 training log-likelihood partials over all parts' row-sorted entries
+// (n_blocks partials), then an in-order sum of n partials into *out.
 hipError_t launch_loglik(const float *W, const float *Hs, const int32_t *row_of_entry,
                          const Entry *ent, int64_t n, int K, int Kp, double beta, double phi,
-                         double mu_floor, double *partials, int n_blocks, double *out,
-                         hipStream_t stream);
+                         double mu_floor, double *partials, int n_blocks, hipStream_t stream);
+hipError_t launch_sum_in_order(const double *partials, int n, double *out, hipStream_t stream);
 
 }  // namespace psgld

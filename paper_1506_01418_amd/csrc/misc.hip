@@ -71,6 +71,35 @@ __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+// Same for the training cells of dense blocks: blockIdx.y is the block.
+__global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
+    const float *W, const float *Hs, const DenseBlock *blocks, const float *val, const uint8_t *mask, int K,
+    int Kp, double beta, double phi, double mu_floor, double *partials, int per_block)
+{
+    __shared__ double red[kLLThreads];
+    const DenseBlock blk = blocks[blockIdx.y];
+    const int64_t cells = static_cast<int64_t>(blk.m) * blk.n;
+    double acc = 0.0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kLLThreads + threadIdx.x; e < cells;
+         e += static_cast<int64_t>(per_block) * kLLThreads) {
+        if (mask[blk.v_off + e] != kMaskTrain) continue;
+        const int i = static_cast<int>(e / blk.n), j = static_cast<int>(e % blk.n);
+        const float *w = W + static_cast<size_t>(blk.row0 + i) * Kp;
+        const float *h = Hs + static_cast<size_t>(blk.col0 + j) * Kp;
+        double mu = 0.0;
+        for (int k = 0; k < K; ++k) mu += static_cast<double>(w[k]) * static_cast<double>(h[k]);
+        if (beta < 2.0 && mu < mu_floor) mu = mu_floor;
+        acc -= dbeta(static_cast<double>(val[blk.v_off + e]), mu, beta) / phi;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kLLThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[static_cast<size_t>(blockIdx.y) * per_block + blockIdx.x] = red[0];
+}
+
 // Sums the per-block partials in index order (deterministic).
 __global__ void sum_in_order_kernel(const double *partials, int n, double *out)
 {
@@ -105,14 +134,26 @@ hipError_t launch_normals(int64_t n, uint64_t seed, const int64_t *t, const uint
 
 hipError_t launch_loglik(const float *W, const float *Hs, const int32_t *row_of_entry,
                          const Entry *ent, int64_t n, int K, int Kp, double beta, double phi,
-                         double mu_floor, double *partials, int n_blocks, double *out,
-                         hipStream_t stream)
+                         double mu_floor, double *partials, int n_blocks, hipStream_t stream)
 {
     hipLaunchKernelGGL(loglik_partial_kernel, dim3(n_blocks), dim3(kLLThreads), 0, stream, W, Hs,
                        row_of_entry, ent, n, K, Kp, beta, phi, mu_floor, partials);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(sum_in_order_kernel, dim3(1), dim3(64), 0, stream, partials, n_blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
+                               const float *val, const uint8_t *mask, int K, int Kp, double beta, double phi,
+                               double mu_floor, double *partials, int per_block, hipStream_t stream)
+{
+    if (n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(dense_loglik_partial_kernel, dim3(per_block, n_blocks), dim3(kLLThreads), 0, stream, W,
+                       Hs, blocks, val, mask, K, Kp, beta, phi, mu_floor, partials, per_block);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_in_order(const double *partials, int n, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sum_in_order_kernel, dim3(1), dim3(64), 0, stream, partials, n, out);
     return hipGetLastError();
 }
 

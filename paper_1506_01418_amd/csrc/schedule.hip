@@ -41,7 +41,8 @@ struct Staged {
 
 void build_part_schedule(const int32_t *pre_r, const int32_t *pre_c, int64_t I, int64_t J,
                          const std::vector<int32_t> &row_piece, const std::vector<int32_t> &col_piece,
-                         int32_t B, int32_t p, int lpg, const ScheduleParams &prm, PartSchedule &out)
+                         int32_t B, int32_t p, int lpg, const ScheduleParams &prm, const uint8_t *skip_block,
+                         PartSchedule &out)
 {
     const int Q = sparse_block_threads() / lpg;
     const int qlog = ceil_log2(Q);
@@ -80,6 +81,7 @@ void build_part_schedule(const int32_t *pre_r, const int32_t *pre_c, int64_t I, 
 
     out.n_splits = 0;
     for (int32_t b = 0; b < B; ++b) {
+        if (skip_block && skip_block[b]) continue;
         for (int side = 0; side < 2; ++side) {
             const std::vector<int32_t> &items = side == 0 ? rows_of[b] : cols_of[b];
             const int32_t *pre = side == 0 ? pre_r : pre_c;

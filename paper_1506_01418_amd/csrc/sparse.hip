@@ -96,20 +96,10 @@ __device__ __forceinline__ void add4(float4 &acc, const float4 &o)
     acc.w += o.w;
 }
 
-// d/dmu log TW(v; mu, phi, beta) = (v - mu) mu^(beta-2) / phi, with the mean
-// floored when beta < 2.
 template <int LIK>
 __device__ __forceinline__ float residual(float v, float mu, const SparseIterArgs &a)
 {
-    if constexpr (LIK == LIK_GAUSS) {
-        return (v - mu) * a.inv_phi;
-    } else if constexpr (LIK == LIK_POISSON) {
-        const float m = fmaxf(mu, a.mu_floor);
-        return (v - m) / m * a.inv_phi;
-    } else {
-        const float m = fmaxf(mu, a.mu_floor);
-        return (v - m) * powf(m, a.beta - 2.0f) * a.inv_phi;
-    }
+    return tweedie_residual<LIK>(v, mu, a.inv_phi, a.beta, a.mu_floor);
 }
 
 __device__ __forceinline__ float4 load4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
@@ -331,15 +321,11 @@ hipError_t launch_lpg(const SparseIterArgs &a, int lik, hipStream_t stream)
 {
     const dim3 grid(static_cast<unsigned>(a.n_tasks)), block(kBlockThreads);
     switch (lik) {
-    case LIK_GAUSS:
-        hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GAUSS>), grid, block, 0, stream, a);
-        break;
-    case LIK_POISSON:
-        hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_POISSON>), grid, block, 0, stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GENERAL>), grid, block, 0, stream, a);
-        break;
+    case LIK_GAUSS: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GAUSS>), grid, block, 0, stream, a); break;
+    case LIK_POISSON: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_POISSON>), grid, block, 0, stream, a); break;
+    case LIK_HALF: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_HALF>), grid, block, 0, stream, a); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GAMMA>), grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GENERAL>), grid, block, 0, stream, a); break;
     }
     return hipGetLastError();
 }

@@ -8,6 +8,8 @@ import paper_1506_01418_amd as pkg
 # c_x = |x_old| + eps (s_p G+_x + |prior'(x_old)|) + sigma R_x (the magnitude of
 # every term that enters the update, computed by the oracle in FP64).
 TOL_FP32 = 1e-5
+# The dense blocks' BF16 path rounds the MFMA operands (W, H, E) to bfloat16.
+TOL_BF16 = 2e-2
 
 
 def oracle_config(wl, flags=0):
@@ -23,11 +25,11 @@ def scaled_error(x_gpu, x_ref, bound):
     return e
 
 
-def step_parity(wl, steps_before=0, flags=0, sampler=None, **overrides):
+def step_parity(wl, steps_before=0, flags=0, sampler=None, dense=False, **overrides):
     """Runs the GPU chain `steps_before` iterations, hands its FP32 state to
     the oracle, then takes one more iteration on both and returns the worst
     scaled error over W and H (and the sampler)."""
-    s = sampler or pkg.PSGLD.from_workload(wl, test_flags=flags, **overrides)
+    s = sampler or pkg.PSGLD.from_workload(wl, dense=dense, test_flags=flags, **overrides)
     if steps_before:
         s.step(steps_before, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     Wg, Hg = s.factors()

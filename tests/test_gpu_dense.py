@@ -1,0 +1,134 @@
+"""GPU-vs-oracle parity of the dense-block path (MFMA), through the C ABI.
+
+psgld_load_dense runs blocks whose training density exceeds the threshold
+(and that have at most 128 rows) on the matrix-core kernels; the oracle sees
+the same training cells as coordinates.  FP32 operands are held to the FP32
+single-step bound, BF16 operands to the BF16 bound."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1506_01418_amd as pkg
+import workloads
+from parity import TOL_BF16, TOL_FP32, oracle_config, step_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def dense_case(I, J, K, B, beta, density=0.9, seed=0, prior="exponential", mirror=True, block_density=None):
+    """A dense-matrix workload; block_density(b, c) overrides the density."""
+    rng = np.random.default_rng(seed)
+    Wt = rng.gamma(2.0, 0.5, (I, max(2, K // 2)))
+    Ht = rng.gamma(1.0, 1.0, (max(2, K // 2), J))
+    mu = Wt @ Ht
+    V = (mu * rng.gamma(4.0, 0.25, (I, J)) + 0.05).astype(np.float32)
+    rp, cp = oracle.partition(I, B), oracle.partition(J, B)
+    dens = np.full((I, J), density)
+    if block_density is not None:
+        dens = np.array([[block_density(rp[i], cp[j]) for j in range(J)] for i in range(I)])
+    u = rng.random((I, J))
+    mask = (u < dens).astype(np.uint8)
+    held = (u >= dens) & (u < dens + 0.05)
+    row, col = np.nonzero(mask)
+    hrow, hcol = np.nonzero(held)
+    val = V[row, col]
+    W0, H0 = workloads.init_factors(np.random.default_rng(seed + 1), I, J, K, float(val.mean()), mirror)
+    a = workloads.step_scale(row, col, val, I, J, beta, 1.0)
+    return workloads.Workload("dense_case", I, J, K, B, beta, 1.0, prior, 1.0, 1.0, mirror, a, 1.0, 0.51,
+                              seed + 2, 10, 0, 1, row.astype(np.int32), col.astype(np.int32), val,
+                              hrow.astype(np.int32), hcol.astype(np.int32), V[hrow, hcol], W0, H0,
+                              dense=V, mask=mask)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("steps_before", [0, 5])
+def test_dense_poisson_256_parity(bf16, steps_before):
+    wl = workloads.dense_poisson()
+    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    err, s = step_parity(wl, steps_before, dense=True, precision=prec)
+    s.close()
+    assert err <= (TOL_BF16 if bf16 else TOL_FP32), err
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("case", ["cpois_K64_m65", "gauss_K20_ragged", "gamma_K8_B5", "unequal_heights"])
+def test_dense_parity_shapes(case, bf16):
+    wl = {"cpois_K64_m65": lambda: dense_case(130, 1000, 64, 2, 0.5, seed=1),
+          "gauss_K20_ragged": lambda: dense_case(201, 333, 20, 3, 2.0, seed=2, prior="gaussian",
+                                                 mirror=False),
+          "gamma_K8_B5": lambda: dense_case(150, 170, 8, 5, 0.0, seed=3),
+          # pieces of 33, 32 and 32 rows: blocks of one part pad to different heights
+          "unequal_heights": lambda: dense_case(97, 400, 16, 3, 1.0, seed=9)}[case]()
+    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    for steps in (0, 4):
+        err, s = step_parity(wl, steps, dense=True, precision=prec)
+        s.close()
+        assert err <= (TOL_BF16 if bf16 else TOL_FP32), (case, steps, err)
+
+
+def test_mixed_dense_and_sparse_blocks():
+    """Diagonal blocks dense, the others below the threshold: each part mixes
+    the dense kernels and the coordinate kernel."""
+    wl = dense_case(256, 240, 16, 4, 1.0, seed=4, block_density=lambda b, c: 0.8 if b == c else 0.1)
+    s = pkg.PSGLD.from_workload(wl, dense=True)
+    for t in range(6):
+        err, _ = step_parity(wl, 0, sampler=s)
+        assert err <= TOL_FP32, (t, err)
+    s.close()
+
+
+def test_tall_blocks_fall_back_to_coordinates():
+    wl = dense_case(300, 90, 12, 2, 1.0, seed=5)      # 150 rows per block > 128
+    err, s = step_parity(wl, 3, dense=True)
+    s.close()
+    assert err <= TOL_FP32
+
+
+def test_dense_heldout_moments_and_loglik():
+    wl = dense_case(160, 400, 16, 4, 1.0, seed=6)
+    wl.burn_in, wl.thin = 4, 2
+    s = pkg.PSGLD.from_workload(wl, dense=True)
+    s.step(16, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    ch = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+    ch.run(16)
+    np.testing.assert_allclose(s.heldout_predictions(), ch.heldout_prediction(), rtol=1e-4)
+    mW, mH = s.posterior_mean()
+    rW, rH = ch.posterior_mean()
+    np.testing.assert_allclose(mW, rW, rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(mH, rH, rtol=1e-4, atol=1e-6)
+    n_p, N = s.part_sizes()
+    assert N == len(wl.row) and np.array_equal(n_p, ch.part_sizes())
+    Wg, Hg = s.factors()
+    ref = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, Wg, Hg)
+    assert s.log_likelihood() == pytest.approx(ref.loglik(), rel=1e-10)
+    with pytest.raises(pkg.PsgldError):
+        t = pkg.PSGLD.from_workload(wl, dense=True)
+        t.load_heldout(wl.row[:2], wl.col[:2])      # training cells
+    s.close()
+
+
+def test_dense_kernels_are_the_ones_running():
+    """The precision option only affects dense blocks: if the dense kernels
+    run, BF16 and FP32 operands give different bits; for a context whose
+    blocks are all below the threshold they give the same bits."""
+    wl = dense_case(128, 300, 16, 2, 1.0, seed=8)
+    outs = {}
+    for thr in (0.3, 0.99):
+        for prec in (pkg.PSGLD_FP32, pkg.PSGLD_BF16_DENSE):
+            s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_threshold=thr)
+            s.step(2, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+            outs[thr, prec] = s.factors()[0]
+            s.close()
+    assert not np.array_equal(outs[0.3, pkg.PSGLD_FP32], outs[0.3, pkg.PSGLD_BF16_DENSE])
+    assert np.array_equal(outs[0.99, pkg.PSGLD_FP32], outs[0.99, pkg.PSGLD_BF16_DENSE])
+
+
+def test_dense_runs_are_bitwise_reproducible():
+    wl = dense_case(130, 700, 64, 2, 0.5, seed=7)
+    out = []
+    for _ in range(2):
+        s = pkg.PSGLD.from_workload(wl, dense=True, precision=pkg.PSGLD_BF16_DENSE)
+        s.step(4, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        out.append(s.factors())
+        s.close()
+    assert all(np.array_equal(a, b) for a, b in zip(*out))

@@ -1,0 +1,38 @@
+"""Parity at the benchmark's sizes and launch configuration.
+
+The headline workload (70,000 x 10,700, 9M training entries, K = 50, B = 32)
+is stepped on the GPU with the schedule bench.py tunes, and single steps
+(t = 0 and mid-run) are compared element by element with the FP64 oracle's
+full step.  The dense spectrogram-shaped workload keeps its block shape
+(1025 rows in 16 pieces of 64-65 rows, K = 64, beta = 0.5) on 4,000 columns so
+the oracle finishes in seconds."""
+import numpy as np
+import pytest
+
+import paper_1506_01418_amd as pkg
+import workloads
+from parity import TOL_BF16, TOL_FP32, step_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def test_sparse_ratings_full_size_step_parity():
+    wl = workloads.sparse_ratings()
+    s = pkg.PSGLD.from_workload(wl)
+    s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
+    err0, _ = step_parity(wl, 0, sampler=s)
+    err1, _ = step_parity(wl, 6, sampler=s)
+    s.close()
+    assert err0 <= TOL_FP32 and err1 <= TOL_FP32, (err0, err1)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_dense_tweedie_block_shape_parity(bf16):
+    wl = workloads.dense_tweedie(J=4000, name="dense_tweedie_1025x4k")
+    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec)
+    err0, _ = step_parity(wl, 0, sampler=s)
+    err1, _ = step_parity(wl, 5, sampler=s)
+    s.close()
+    tol = TOL_BF16 if bf16 else TOL_FP32
+    assert err0 <= tol and err1 <= tol, (err0, err1)
