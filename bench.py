@@ -137,6 +137,74 @@ def cpu_baseline(wl, iters):
                       f"of the same workload, single-threaded FP64 C, {dt:.1f} s incl. its setup"}
 
 
+def serve_main(args):
+    """Serving stream: jobs arrive as a Poisson process (rate 0: all at once),
+    are admitted FIFO under the HBM budget and stepped together; latency is
+    finish minus arrival on the host clock.  value = training-entry updates of
+    all jobs / makespan (first arrival to last finish)."""
+    import paper_1506_01418_amd as pkg
+
+    t_gen = time.perf_counter()
+    jobs = [workloads.serving_job(j, T=args.job_iters, burn_in=args.job_iters // 2) for j in range(args.jobs)]
+    arrivals = workloads.job_arrivals(args.jobs, args.rate)
+    print(f"[bench] {args.jobs} jobs generated in {time.perf_counter() - t_gen:.1f} s "
+          f"({sum(wl.nnz for wl in jobs)} training entries, {sum(wl.dense is not None for wl in jobs)} dense)",
+          file=sys.stderr, flush=True)
+    srv = pkg.Server(int(args.budget_gib * (1 << 30)), max_active=args.max_active,
+                     iters_per_tick=args.iters_per_tick)
+    # warm-up: one small job through the whole path (kernel loading, allocator)
+    wid = srv.submit(workloads.serving_job(10_000, T=args.iters_per_tick, burn_in=0), args.iters_per_tick)
+    while srv.tick()[:2] != (0, 0):
+        pass
+    srv.release(wid)
+    ids, finish = {}, {}
+    nxt, t0 = 0, time.perf_counter()
+    ticks, max_running = 0, 0
+    while len(finish) < args.jobs:
+        now = time.perf_counter() - t0
+        while nxt < args.jobs and arrivals[nxt] <= now:
+            wl = jobs[nxt]
+            ids[srv.submit(wl, args.job_iters, dense=wl.dense is not None)] = nxt
+            nxt += 1
+        running, queued, retired = srv.tick()
+        ticks += 1
+        max_running = max(max_running, running)
+        if retired:
+            now = time.perf_counter() - t0
+            for jid, j in list(ids.items()):
+                st = srv.info(jid)["state"]
+                if st in (pkg.PSGLD_JOB_DONE, pkg.PSGLD_JOB_FAILED):
+                    if st == pkg.PSGLD_JOB_FAILED:
+                        raise SystemExit(f"job {j} failed: {srv.error(jid)}")
+                    finish[j] = now
+                    srv.release(jid)
+                    del ids[jid]
+        if running == 0 and queued == 0 and nxt < args.jobs:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    srv.close()
+    lat = np.array([finish[j] - arrivals[j] for j in range(args.jobs)])
+    makespan = max(finish.values()) - float(arrivals[0])
+    updates = float(sum(wl.nnz * args.job_iters for wl in jobs))
+    value = updates / makespan
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    print(f"[bench] serve: {args.jobs} jobs in {makespan:.2f} s, p50 {p50 * 1e3:.1f} ms, p99 {p99 * 1e3:.1f} ms, "
+          f"{value:.4g} updates/s, {ticks} ticks, at most {max_running} running", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.job_iters,
+        "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve_c5_{args.jobs}jobs", "jobs": args.jobs, "rate_per_s": args.rate,
+                   "hbm_budget_gib": args.budget_gib, "iters_per_job": args.job_iters,
+                   "iters_per_tick": args.iters_per_tick, "max_active": args.max_active,
+                   "parallelism": "single-gpu"},
+        "serving": {"p50_ms": p50 * 1e3, "p99_ms": p99 * 1e3, "jobs_per_s": args.jobs / makespan,
+                    "makespan_s": makespan, "ticks": ticks, "max_running": max_running},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,11 +215,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
                     help="operand precision of the dense-block kernels")
+    ap.add_argument("--jobs", type=int, default=200, help="serve_c5: number of jobs")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve_c5: arrivals per second (0: all at once)")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="serve_c5: HBM budget of the running jobs")
+    ap.add_argument("--iters-per-tick", type=int, default=25, help="serve_c5: iterations per job per tick")
+    ap.add_argument("--max-active", type=int, default=64, help="serve_c5: running jobs at most")
+    ap.add_argument("--job-iters", type=int, default=500, help="serve_c5: iterations per job")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve_c5":
+        serve_main(args)
+        return
 
     import paper_1506_01418_amd as pkg
 

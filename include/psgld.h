@@ -103,11 +103,15 @@ typedef struct {
     void *stream;             /* hipStream_t to run on; NULL = the library's own stream */
     uint32_t test_flags;      /* PSGLD_TEST_* (test use only) */
     int32_t device;           /* HIP device ordinal */
+    int32_t graph_iters;      /* iterations per captured HIP graph in psgld_step:
+                                 0 = one cycle of B parts repeated to at least 32
+                                 iterations; < 0 = never capture (one launch
+                                 sequence per iteration) */
 } psgld_options;
 
 /* Fills *opt with the defaults: seed 0, burn_in 0, thin 1, FP32,
  * dense_threshold 0.3, mu_floor 1e-6, contiguous pieces, own stream,
- * no test flags, device 0. */
+ * no test flags, device 0, graph_iters 0. */
 void psgld_default_options(psgld_options *opt);
 
 /* Creates a context for an I x J matrix, rank K (1..256), B x B blocks
@@ -150,9 +154,26 @@ psgld_status psgld_set_factors(psgld_ctx *ctx, const float *W, const float *H);
 
 /* Runs n_iter >= 0 iterations of Algorithm 1, asynchronously on the
  * context's stream, continuing from the context's iteration counter t.
+ * Runs of graph_iters iterations are captured once into a HIP graph (per
+ * starting part and ping-pong phase) and replayed; the graph reads the
+ * iteration from a device counter and the step sizes from a device table,
+ * so replays are bitwise identical to launching the iterations one by one.
  * E_STATE before data and factors are set.  A non-finite value produced by
  * these iterations is reported as E_NUMERIC by the next synchronising call. */
 psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule *sched);
+
+/* Runs n_iter[j] >= 0 iterations of context ctxs[j] with schedule
+ * scheds[j], for j < n, interleaved iteration by iteration.  Contexts with
+ * only coordinate-stored blocks are grouped by kernel variant (rank class and
+ * likelihood branch) and up to 64 of them share one launch per iteration: the
+ * launch reads a device table of the contexts, and each context's iteration
+ * from its device clock.  Contexts with dense blocks are launched one by one
+ * inside the same loop.  Each context's results are bitwise those of
+ * psgld_step on it alone: the contexts share no memory.  All contexts must be
+ * distinct and share one device and one stream (options.stream), else E_ARG;
+ * each needs data and factors (E_STATE).  Asynchronous like psgld_step. */
+psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *n_iter,
+                              const psgld_eps_schedule *scheds);
 
 /* Tunes the work schedule of the coordinate-stored blocks (how many entries
  * one lane group takes before an item is spread over more groups) on this
@@ -241,6 +262,97 @@ psgld_status psgld_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t 
 psgld_status psgld_normals(int64_t n, uint64_t seed, const int64_t *t, const uint32_t *stream,
                            const int64_t *index, int32_t K, float *z, float *radius,
                            int32_t device);
+
+/* ---------------------------------------------------------------------
+ * Serving: many independent PSGLD runs ("jobs") on one device.
+ *
+ * Jobs wait in a FIFO queue.  A job is admitted when fewer than max_active
+ * jobs run and the device bytes it will need (an upper estimate before it is
+ * loaded, its context's actual allocation afterwards) fit in hbm_budget
+ * beside the running jobs; the queue head blocks those behind it, so jobs
+ * start in submission order.  Each tick admits what fits, advances every
+ * running job by up to iters_per_tick iterations with psgld_step_batch (one
+ * launch per kernel variant for all coordinate-stored jobs), waits for the
+ * device, and retires jobs that reached their n_iter: their FP64 posterior
+ * moments and held-out RMSE are copied to host memory and their device
+ * memory is freed.  A job's results are bitwise those of the same run on a
+ * context of its own.  A server is used by one host thread at a time.
+ * --------------------------------------------------------------------- */
+typedef struct psgld_server psgld_server;
+
+typedef struct {
+    int64_t hbm_budget;       /* device bytes the running jobs may hold; > 0 */
+    int32_t max_active;       /* running jobs at most; >= 1 */
+    int32_t iters_per_tick;   /* iterations per job per tick; >= 1 */
+    int32_t device;           /* HIP device ordinal */
+} psgld_server_options;
+
+/* One complete run.  Data as for psgld_load_coo (row != NULL) or
+ * psgld_load_dense (row == NULL, dense != NULL, mask may be NULL); held-out
+ * cells as for psgld_load_heldout (n_heldout may be 0); W0 (I x K) and H0
+ * (K x J) as for psgld_set_factors.  The job runs n_iter >= 1 iterations of
+ * schedule sched with the given seed, burn-in, thinning, precision and dense
+ * threshold (other options at their defaults). */
+typedef struct {
+    int64_t I, J;
+    int32_t K, B;
+    psgld_likelihood lik;
+    psgld_prior prior;
+    uint64_t seed;
+    int64_t burn_in;
+    int32_t thin;
+    int32_t precision;
+    double dense_threshold;
+    psgld_eps_schedule sched;
+    int64_t n_iter;
+    int64_t nnz;
+    const int32_t *row, *col;
+    const float *val;
+    const float *dense;
+    const uint8_t *mask;
+    int64_t n_heldout;
+    const int32_t *hrow, *hcol;
+    const float *hval;
+    const float *W0, *H0;
+} psgld_job;
+
+enum { PSGLD_JOB_QUEUED = 0, PSGLD_JOB_RUNNING = 1, PSGLD_JOB_DONE = 2, PSGLD_JOB_FAILED = 3 };
+
+psgld_status psgld_server_create(const psgld_server_options *opt, psgld_server **out);
+
+/* Upper estimate of the device bytes a job's context allocates. */
+psgld_status psgld_server_estimate_bytes(const psgld_job *job, int64_t *bytes);
+
+/* Copies the job's inputs and queues it; *id receives its handle.  E_ARG if
+ * the job is malformed or its estimate exceeds the whole budget. */
+psgld_status psgld_server_submit(psgld_server *srv, const psgld_job *job, int64_t *id);
+
+/* One tick (see above).  Outputs (each may be NULL): jobs running after the
+ * tick, jobs still queued, jobs retired by this tick.  A job whose load or
+ * run fails is marked FAILED (its message in psgld_server_job_error) and the
+ * tick goes on; only device errors of the shared stream fail the tick. */
+psgld_status psgld_server_tick(psgld_server *srv, int32_t *n_running, int32_t *n_queued, int32_t *n_retired);
+
+/* State, iterations done, estimated and actual device bytes (actual is 0
+ * until admitted) of a job.  Any output may be NULL. */
+psgld_status psgld_server_job_info(psgld_server *srv, int64_t id, int32_t *state, int64_t *iterations,
+                                   int64_t *est_bytes, int64_t *bytes);
+
+/* Results of a DONE job: posterior means and variances (I x K and K x J,
+ * FP64, as psgld_posterior_mean/var) and held-out RMSE (NaN without held-out
+ * values).  Any output may be NULL.  E_STATE unless the job is DONE. */
+psgld_status psgld_server_job_result(psgld_server *srv, int64_t id, double *W_mean, double *H_mean,
+                                     double *W_var, double *H_var, double *heldout_rmse);
+
+/* Forgets a finished (DONE or FAILED) job and its results. */
+psgld_status psgld_server_release(psgld_server *srv, int64_t id);
+
+/* Message of the last failing call on srv (or of a FAILED job). */
+const char *psgld_server_last_error(const psgld_server *srv);
+const char *psgld_server_job_error(const psgld_server *srv, int64_t id);
+
+/* Waits for the device and frees every job and the server. */
+void psgld_server_destroy(psgld_server *srv);
 
 #ifdef __cplusplus
 }

@@ -60,7 +60,27 @@ class psgld_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("burn_in", C.c_int64), ("thin", C.c_int32),
                 ("precision", C.c_int32), ("dense_threshold", C.c_double),
                 ("mu_floor", C.c_double), ("row_piece", C.c_void_p), ("col_piece", C.c_void_p),
-                ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32)]
+                ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32),
+                ("graph_iters", C.c_int32)]
+
+
+class psgld_server_options(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("iters_per_tick", C.c_int32),
+                ("device", C.c_int32)]
+
+
+class psgld_job(C.Structure):
+    _fields_ = [("I", C.c_int64), ("J", C.c_int64), ("K", C.c_int32), ("B", C.c_int32),
+                ("lik", psgld_likelihood), ("prior", psgld_prior), ("seed", C.c_uint64),
+                ("burn_in", C.c_int64), ("thin", C.c_int32), ("precision", C.c_int32),
+                ("dense_threshold", C.c_double), ("sched", psgld_eps_schedule), ("n_iter", C.c_int64),
+                ("nnz", C.c_int64), ("row", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("dense", C.c_void_p), ("mask", C.c_void_p), ("n_heldout", C.c_int64),
+                ("hrow", C.c_void_p), ("hcol", C.c_void_p), ("hval", C.c_void_p),
+                ("W0", C.c_void_p), ("H0", C.c_void_p)]
+
+
+PSGLD_JOB_QUEUED, PSGLD_JOB_RUNNING, PSGLD_JOB_DONE, PSGLD_JOB_FAILED = 0, 1, 2, 3
 
 
 _P = C.c_void_p
@@ -77,6 +97,7 @@ SIGNATURES = {
     "psgld_load_heldout": ([_P, _I64, _P, _P, _P], _ST),
     "psgld_set_factors": ([_P, _P, _P], _ST),
     "psgld_step": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
+    "psgld_step_batch": ([_P, C.c_int32, _P, _P], _ST),
     "psgld_sync": ([_P], _ST),
     "psgld_tune": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(psgld_eps_schedule), C.POINTER(C.c_int32)], _ST),
     "psgld_get_factors": ([_P, _P, _P], _ST),
@@ -93,6 +114,16 @@ SIGNATURES = {
     "psgld_memory_bytes": ([_P, C.POINTER(_I64)], _ST),
     "psgld_get_stream": ([_P, C.POINTER(_P)], _ST),
     "psgld_last_error": ([_P], C.c_char_p),
+    "psgld_server_create": ([C.POINTER(psgld_server_options), _P], _ST),
+    "psgld_server_estimate_bytes": ([C.POINTER(psgld_job), _P], _ST),
+    "psgld_server_submit": ([_P, C.POINTER(psgld_job), _P], _ST),
+    "psgld_server_tick": ([_P, _P, _P, _P], _ST),
+    "psgld_server_job_info": ([_P, _I64, _P, _P, _P, _P], _ST),
+    "psgld_server_job_result": ([_P, _I64, _P, _P, _P, _P, _P], _ST),
+    "psgld_server_release": ([_P, _I64], _ST),
+    "psgld_server_last_error": ([_P], C.c_char_p),
+    "psgld_server_job_error": ([_P, _I64], C.c_char_p),
+    "psgld_server_destroy": ([_P], None),
     "psgld_destroy": ([_P], None),
     "psgld_philox_blocks": ([_I64, _P, _P, _P, C.c_int32], _ST),
     "psgld_normals": ([_I64, C.c_uint64, _P, _P, _P, C.c_int32, _P, _P, C.c_int32], _ST),
@@ -171,6 +202,18 @@ def psgld_set_factors(ctx, W, H):
 
 def psgld_step(ctx, n_iter, sched: psgld_eps_schedule):
     _check(lib().psgld_step(ctx, int(n_iter), C.byref(sched)), ctx)
+
+
+def psgld_step_batch(ctxs, n_iter, scheds):
+    """n_iter[j] iterations of ctxs[j] with scheds[j] (psgld_eps_schedule)."""
+    n = len(ctxs)
+    arr = (C.c_void_p * max(n, 1))(*ctxs)
+    its = _arr(n_iter, np.int64)
+    sch = (psgld_eps_schedule * max(n, 1))(*scheds)
+    st = lib().psgld_step_batch(arr, n, _ptr(its), C.cast(sch, C.c_void_p))
+    if st != PSGLD_OK:
+        bad = next((c for c in ctxs if lib().psgld_last_error(c)), ctxs[0] if ctxs else None)
+        _check(st, bad)
 
 
 def psgld_tune(ctx, candidates, iters, sched: psgld_eps_schedule) -> int:
@@ -301,7 +344,7 @@ class PSGLD:
     def __init__(self, I, J, K, B, beta=2.0, phi=1.0, prior="gaussian", lambda_w=1.0,
                  lambda_h=1.0, mirror=False, seed=0, burn_in=0, thin=1, precision=PSGLD_FP32,
                  dense_threshold=0.3, mu_floor=1e-6, row_piece=None, col_piece=None,
-                 stream: Optional[int] = None, test_flags=0, device=0):
+                 stream: Optional[int] = None, test_flags=0, device=0, graph_iters=0):
         self.I, self.J, self.K, self.B = int(I), int(J), int(K), int(B)
         lik = psgld_likelihood(beta, phi)
         pr = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
@@ -313,7 +356,7 @@ class PSGLD:
         opt.row_piece = _ptr(self._pieces[0])
         opt.col_piece = _ptr(self._pieces[1])
         opt.stream = stream or None
-        opt.test_flags, opt.device = test_flags, device
+        opt.test_flags, opt.device, opt.graph_iters = test_flags, device, graph_iters
         self.ctx = psgld_create(self.I, self.J, self.K, self.B, lik, pr, opt)
         self.n_heldout = 0
 
@@ -352,6 +395,13 @@ class PSGLD:
 
     def step(self, n_iter, a, t0=1.0, gamma=0.51):
         psgld_step(self.ctx, n_iter, psgld_eps_schedule(a, t0, gamma))
+
+    @staticmethod
+    def step_batch(samplers, n_iter, schedules):
+        """Steps several samplers together (psgld_step_batch); n_iter and
+        schedules ((a, t0, gamma) tuples) are per sampler."""
+        psgld_step_batch([s.ctx for s in samplers], list(n_iter),
+                         [psgld_eps_schedule(*sc) for sc in schedules])
 
     def tune(self, a, t0=1.0, gamma=0.51, candidates=(16, 32, 64, 128), iters=0):
         return psgld_tune(self.ctx, candidates, iters, psgld_eps_schedule(a, t0, gamma))
@@ -414,3 +464,115 @@ class PSGLD:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------------ serving
+def _server_check(status, srv):
+    if status != PSGLD_OK:
+        msg = lib().psgld_server_last_error(srv)
+        raise PsgldError(status, msg.decode() if msg else "")
+
+
+def psgld_job_from(wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3):
+    """A psgld_job for a workload (see workloads.Workload) and the arrays it
+    points to, which must stay alive until the job is submitted."""
+    keep = {}
+
+    def ref(name, a, dtype):
+        if a is None:
+            return None
+        keep[name] = _arr(a, dtype)
+        return keep[name].ctypes.data
+
+    j = psgld_job()
+    j.I, j.J, j.K, j.B = wl.I, wl.J, wl.K, wl.B
+    j.lik = psgld_likelihood(wl.beta, wl.phi)
+    j.prior = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if wl.prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
+                          wl.lambda_w, wl.lambda_h, int(bool(wl.mirror)))
+    j.seed, j.burn_in, j.thin = wl.seed, wl.burn_in, wl.thin
+    j.precision, j.dense_threshold = precision, dense_threshold
+    j.sched = psgld_eps_schedule(wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    j.n_iter = int(n_iter)
+    if dense:
+        j.nnz = 0
+        j.dense = ref("dense", wl.dense, np.float32)
+        j.mask = ref("mask", wl.mask, np.uint8)
+    else:
+        j.nnz = len(wl.row)
+        j.row, j.col = ref("row", wl.row, np.int32), ref("col", wl.col, np.int32)
+        j.val = ref("val", wl.val, np.float32)
+    j.n_heldout = len(wl.hrow)
+    if j.n_heldout:
+        j.hrow, j.hcol = ref("hrow", wl.hrow, np.int32), ref("hcol", wl.hcol, np.int32)
+        j.hval = ref("hval", wl.hval, np.float32)
+    j.W0, j.H0 = ref("W0", wl.W0, np.float32), ref("H0", wl.H0, np.float32)
+    return j, keep
+
+
+def psgld_server_estimate_bytes(job) -> int:
+    out = C.c_int64()
+    st = lib().psgld_server_estimate_bytes(C.byref(job), C.byref(out))
+    if st != PSGLD_OK:
+        raise PsgldError(st, "malformed job")
+    return out.value
+
+
+class Server:
+    """Serving loop (psgld_server_*): jobs admitted FIFO under an HBM budget
+    and stepped together, iters_per_tick iterations per tick."""
+
+    def __init__(self, hbm_budget, max_active=64, iters_per_tick=25, device=0):
+        opt = psgld_server_options(int(hbm_budget), int(max_active), int(iters_per_tick), int(device))
+        out = C.c_void_p()
+        st = lib().psgld_server_create(C.byref(opt), C.byref(out))
+        if st != PSGLD_OK:
+            raise PsgldError(st, "psgld_server_create failed")
+        self.srv = out.value
+        self.shapes = {}
+
+    def submit(self, wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3) -> int:
+        job, keep = psgld_job_from(wl, n_iter, dense, precision, dense_threshold)
+        jid = C.c_int64()
+        _server_check(lib().psgld_server_submit(self.srv, C.byref(job), C.byref(jid)), self.srv)
+        del keep
+        self.shapes[jid.value] = (wl.I, wl.J, wl.K)
+        return jid.value
+
+    def tick(self):
+        r, q, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _server_check(lib().psgld_server_tick(self.srv, C.byref(r), C.byref(q), C.byref(d)), self.srv)
+        return r.value, q.value, d.value
+
+    def info(self, jid):
+        st, it, est, b = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        _server_check(lib().psgld_server_job_info(self.srv, int(jid), C.byref(st), C.byref(it), C.byref(est),
+                                                  C.byref(b)), self.srv)
+        return {"state": st.value, "iterations": it.value, "est_bytes": est.value, "bytes": b.value}
+
+    def error(self, jid) -> str:
+        m = lib().psgld_server_job_error(self.srv, int(jid))
+        return m.decode() if m else ""
+
+    def result(self, jid):
+        """(W_mean I x K, H_mean K x J, W_var, H_var, held-out RMSE) of a done job."""
+        I, J, K = self.shapes[jid]
+        Wm, Hm, Wv, Hv = np.zeros((I, K)), np.zeros((K, J)), np.zeros((I, K)), np.zeros((K, J))
+        rmse = C.c_double()
+        _server_check(lib().psgld_server_job_result(self.srv, int(jid), _ptr(Wm), _ptr(Hm), _ptr(Wv), _ptr(Hv),
+                                                    C.byref(rmse)), self.srv)
+        return Wm, Hm, Wv, Hv, rmse.value
+
+    def release(self, jid):
+        _server_check(lib().psgld_server_release(self.srv, int(jid)), self.srv)
+        self.shapes.pop(jid, None)
+
+    def close(self):
+        if self.srv:
+            lib().psgld_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -114,6 +115,25 @@ struct psgld_ctx {
     int ll_blocks = 0;
     int64_t t = 0;
 
+    // step sizes (eps_t, sigma_t) for t in [eps_base, eps_base + eps_cap)
+    float2 *eps_tab = nullptr;
+    int64_t eps_base = 0, eps_cap = 0;
+    psgld_eps_schedule eps_sched{};
+    // device iteration counter read by captured graphs; clock_host is its
+    // value once the enqueued work has run (-1: not set yet)
+    int32_t *clock = nullptr;
+    int64_t clock_host = -1;
+    hipStream_t cap_stream = nullptr;
+    // captured runs of iterations, by (first part, ping-pong buffer, length)
+    std::map<std::tuple<int32_t, int32_t, int64_t>, hipGraphExec_t> graphs;
+    // batched stepping: per-part tables and the context's job description
+    int32_t *task_off_dev = nullptr, *n_tasks_dev = nullptr;
+    float *scale_dev = nullptr;
+    int32_t max_tasks = 0;
+    JobDesc *job_desc = nullptr;
+    JobDesc job_host{};
+    bool job_valid = false;
+
     psgld_status fail(psgld_status s, const std::string &msg)
     {
         err = msg;
@@ -157,6 +177,15 @@ void dev_free(psgld_ctx *c, void *p)
     (void)hipFree(p);
 }
 
+// Destroys every captured graph (after the work already enqueued has run).
+void drop_graphs(psgld_ctx *c)
+{
+    if (c->graphs.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+}
+
 psgld_status ensure_device(psgld_ctx *c)
 {
     if (c->device_ready) return PSGLD_OK;
@@ -173,8 +202,10 @@ psgld_status ensure_device(psgld_ctx *c)
         HIPTRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
+    HIPTRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     psgld_status s = dev_alloc(c, &c->nonfinite, 1);
     if (s) return s;
+    if ((s = dev_alloc(c, &c->clock, 1))) return s;
     const int32_t big = INT_MAX;
     HIPTRY(c, hipMemcpy(c->nonfinite, &big, sizeof(big), hipMemcpyHostToDevice));
     c->device_ready = true;
@@ -194,6 +225,12 @@ psgld_status upload(psgld_ctx *c, T **dst, const std::vector<T> &src)
 int32_t part_of(const psgld_ctx *c, int32_t i, int32_t j)
 {
     return (c->col_piece[j] - c->row_piece[i] + c->B) % c->B;
+}
+
+// s_p = N / n_p in FP64, rounded once (0 for a part without entries).
+float part_scale(const psgld_ctx *c, int32_t p)
+{
+    return c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
 }
 
 // Builds every part's work schedule for c->sched and uploads it, replacing
@@ -219,6 +256,7 @@ psgld_status upload_schedule(psgld_ctx *c)
         max_splits = std::max(max_splits, ps.n_splits);
     }
     HIPTRY(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
     dev_free(c, c->tasks);
     dev_free(c, c->recs);
     dev_free(c, c->split_partial);
@@ -230,6 +268,19 @@ psgld_status upload_schedule(psgld_ctx *c)
     psgld_status s;
     if ((s = upload(c, &c->tasks, tasks))) return s;
     if ((s = upload(c, &c->recs, recs))) return s;
+    std::vector<int32_t> toff(B), ntk(B);
+    c->max_tasks = 0;
+    for (int32_t p = 0; p < B; ++p) {
+        toff[p] = static_cast<int32_t>(c->task_off[p]);
+        ntk[p] = static_cast<int32_t>(c->n_tasks[p]);
+        c->max_tasks = std::max(c->max_tasks, ntk[p]);
+    }
+    dev_free(c, c->task_off_dev);
+    dev_free(c, c->n_tasks_dev);
+    c->task_off_dev = c->n_tasks_dev = nullptr;
+    if ((s = upload(c, &c->task_off_dev, toff))) return s;
+    if ((s = upload(c, &c->n_tasks_dev, ntk))) return s;
+    c->job_valid = false;
     if ((s = dev_alloc(c, &c->split_partial, static_cast<size_t>(max_splits) * c->Kp))) return s;
     if ((s = dev_alloc(c, &c->split_count, static_cast<size_t>(max_splits)))) return s;
     HIPTRY(c, hipMemset(c->split_count, 0, std::max<int32_t>(max_splits, 1) * sizeof(int32_t)));
@@ -428,19 +479,58 @@ psgld_status fetch_factor(psgld_ctx *c, const TDev *dev, int64_t rows, bool tran
     return PSGLD_OK;
 }
 
-// Enqueues iteration t (part t mod B) reading buffer `cur`.  With
-// bookkeeping off (tuning trials) no moments, held-out sums or visit counts
-// are touched.
-psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule *sched, bool bookkeeping)
+// Makes the device step-size table cover iterations [t_begin, t_end) for
+// `sched`.  Refilling waits for the enqueued work; moving or reallocating
+// the table drops the captured graphs, which hold its address.
+psgld_status ensure_eps_table(psgld_ctx *c, const psgld_eps_schedule *sched, int64_t t_begin, int64_t t_end)
+{
+    const bool same = c->eps_tab && sched->a == c->eps_sched.a && sched->t0 == c->eps_sched.t0 &&
+                      sched->gamma == c->eps_sched.gamma;
+    if (same && t_begin >= c->eps_base && t_end <= c->eps_base + c->eps_cap) return PSGLD_OK;
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    int64_t base = c->eps_base, cap = c->eps_cap;
+    if (!c->eps_tab || t_begin < base || t_end > base + cap) {
+        base = t_begin;
+        cap = 4096;
+        while (cap < 2 * (t_end - t_begin)) cap *= 2;
+        drop_graphs(c);
+        dev_free(c, c->eps_tab);
+        c->eps_tab = nullptr;
+        psgld_status s = dev_alloc(c, &c->eps_tab, static_cast<size_t>(cap));
+        if (s) return s;
+    }
+    std::vector<float2> tab(static_cast<size_t>(cap));
+    for (int64_t k = 0; k < cap; ++k) {
+        const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(base + k), -sched->gamma);
+        tab[k] = make_float2(static_cast<float>(eps), static_cast<float>(std::sqrt(2.0 * eps)));
+    }
+    HIPTRY(c, hipMemcpy(c->eps_tab, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice));
+    c->eps_base = base;
+    c->eps_cap = cap;
+    c->eps_sched = *sched;
+    return PSGLD_OK;
+}
+
+// Enqueues one iteration of part p reading ping-pong buffer `cur`.  The
+// iteration index is *clock + k when clock is given (captured graphs), else
+// k.  With bookkeeping off (tuning trials) no moments or held-out sums are
+// touched.
+hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *clock, int32_t k, bool bookkeeping,
+                             hipStream_t stream)
 {
     const int64_t I = c->I, J = c->J;
-    const int32_t p = static_cast<int32_t>(t % c->B);
-    const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(t), -sched->gamma);
+    IterClock clk{};
+    clk.eps_tab = c->eps_tab - c->eps_base;   // indexed by the global iteration
+    clk.clock = clock;
+    clk.k = k;
+    clk.burn_in = static_cast<int32_t>(std::min<int64_t>(c->opt.burn_in, INT32_MAX));
+    clk.thin = c->opt.thin;
+    clk.bookkeeping = bookkeeping ? 1 : 0;
     SparseIterArgs a{};
-    a.x_old[0] = c->W[c->cur];
-    a.x_old[1] = c->H[c->cur];
-    a.x_new[0] = c->W[c->cur ^ 1];
-    a.x_new[1] = c->H[c->cur ^ 1];
+    a.x_old[0] = c->W[cur];
+    a.x_old[1] = c->H[cur];
+    a.x_new[0] = c->W[cur ^ 1];
+    a.x_new[1] = c->H[cur ^ 1];
     a.ptr[0] = c->rowptr + static_cast<size_t>(p) * I;
     a.ptr[1] = c->colptr + static_cast<size_t>(p) * J;
     a.ent[0] = c->ent_r;
@@ -453,9 +543,7 @@ psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule 
     a.K = c->K;
     a.Kp = c->Kp;
     a.nq = c->nq;
-    a.eps = static_cast<float>(eps);
-    a.sigma = static_cast<float>(std::sqrt(2.0 * eps));
-    a.scale = c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
+    a.scale = part_scale(c, p);
     a.lambda[0] = static_cast<float>(c->prior.lambda_w);
     a.lambda[1] = static_cast<float>(c->prior.lambda_h);
     a.inv_phi = static_cast<float>(1.0 / c->lik.phi);
@@ -463,22 +551,21 @@ psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule 
     a.mu_floor = static_cast<float>(c->opt.mu_floor);
     a.seed_lo = static_cast<uint32_t>(c->opt.seed);
     a.seed_hi = static_cast<uint32_t>(c->opt.seed >> 32);
-    a.t = static_cast<uint32_t>(t);
     a.mirror = c->prior.mirror ? 1 : 0;
     a.prior_kind = c->prior.kind;
     a.flags = c->opt.test_flags;
-    const bool post = bookkeeping && t >= c->opt.burn_in;
-    a.do_moments = post && (t - c->opt.burn_in) % c->opt.thin == 0;
+    a.clk = clk;
+    a.clk.has_heldout = c->n_ho > 0 ? 1 : 0;
     for (int side = 0; side < 2; ++side) {
         a.sum[side] = c->sum[side];
         a.sum2[side] = c->sum2[side];
     }
-    a.do_heldout = post && c->n_ho > 0;
     a.ho_ptr = c->ho_ptr ? c->ho_ptr + static_cast<size_t>(p) * I : nullptr;
     a.ho_ent = c->ho_ent;
     a.ho_sum = c->ho_sum;
     a.nonfinite = c->nonfinite;
-    HIPTRY(c, launch_sparse_iter(a, c->lik_kind, c->lpg, c->stream));
+    hipError_t e = launch_sparse_iter(a, c->lik_kind, c->lpg, stream);
+    if (e != hipSuccess) return e;
     if (!c->dblocks_host.empty() && c->dblk_cnt[p] > 0) {
         DenseIterArgs d{};
         d.x_old[0] = a.x_old[0];
@@ -497,8 +584,6 @@ psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule 
         d.K = c->K;
         d.Kp = c->Kp;
         d.KS = c->KS;
-        d.eps = a.eps;
-        d.sigma = a.sigma;
         d.scale = a.scale;
         d.lambda[0] = a.lambda[0];
         d.lambda[1] = a.lambda[1];
@@ -507,24 +592,135 @@ psgld_status launch_iteration(psgld_ctx *c, int64_t t, const psgld_eps_schedule 
         d.mu_floor = a.mu_floor;
         d.seed_lo = a.seed_lo;
         d.seed_hi = a.seed_hi;
-        d.t = a.t;
         d.mirror = a.mirror;
         d.prior_kind = a.prior_kind;
         d.flags = a.flags;
-        d.do_moments = a.do_moments;
+        d.clk = clk;
+        d.clk.has_heldout = c->dheld != nullptr ? 1 : 0;
         for (int side = 0; side < 2; ++side) {
             d.sum[side] = a.sum[side];
             d.sum2[side] = a.sum2[side];
         }
-        d.do_heldout = a.do_heldout && c->dheld != nullptr;
         d.heldout = c->dheld;
         d.ho_sum = c->ho_sum;
         d.nonfinite = c->nonfinite;
-        HIPTRY(c, launch_dense_iter(d, c->lik_kind, c->opt.precision == PSGLD_BF16_DENSE, c->dense_max_m, c->stream));
+        e = launch_dense_iter(d, c->lik_kind, c->opt.precision == PSGLD_BF16_DENSE, c->dense_max_m, stream);
     }
-    if (a.do_moments) c->n_kept++;
-    if (a.do_heldout) c->part_visits[p]++;
-    c->cur ^= 1;
+    return e;
+}
+
+// Host-side record of iteration t having been enqueued with bookkeeping on:
+// kept samples and the visits of each part after burn-in.
+void account_iteration(psgld_ctx *c, int64_t t)
+{
+    if (t < c->opt.burn_in) return;
+    if ((t - c->opt.burn_in) % c->opt.thin == 0) c->n_kept++;
+    if (c->n_ho > 0) c->part_visits[t % c->B]++;
+}
+
+// Iterations per captured graph (0 = do not capture).
+int64_t graph_length(const psgld_ctx *c)
+{
+    if (c->opt.graph_iters < 0) return 0;
+    if (c->opt.graph_iters > 0) return c->opt.graph_iters;
+    return static_cast<int64_t>(c->B) * ((32 + c->B - 1) / c->B);
+}
+
+// The graph of L iterations starting at part r from buffer cur, captured on
+// first use: the iterations read t from the device clock, then the clock
+// advances by L.
+psgld_status get_graph(psgld_ctx *c, int32_t r, int cur, int64_t L, hipGraphExec_t *out)
+{
+    const auto key = std::make_tuple(r, cur, L);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return PSGLD_OK;
+    }
+    HIPTRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < L && e == hipSuccess; ++k)
+        e = enqueue_iteration(c, static_cast<int32_t>((r + k) % c->B), static_cast<int>((cur + k) & 1), c->clock,
+                              static_cast<int32_t>(k), true, c->cap_stream);
+    if (e == hipSuccess) e = launch_advance_clock(c->clock, static_cast<int32_t>(L), c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(c->cap_stream, &graph);
+    if (e == hipSuccess) e = e_end;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return c->fail(PSGLD_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    }
+    c->graphs[key] = exec;
+    *out = exec;
+    return PSGLD_OK;
+}
+
+// The context as the batched kernel reads it; uploaded when it changed
+// (after the work already enqueued has run).
+psgld_status sync_job_desc(psgld_ctx *c)
+{
+    JobDesc d{};
+    for (int b = 0; b < 2; ++b) {
+        d.W[b] = c->W[b];
+        d.H[b] = c->H[b];
+    }
+    d.rowptr = c->rowptr;
+    d.colptr = c->colptr;
+    d.ent[0] = c->ent_r;
+    d.ent[1] = c->ent_c;
+    d.tasks = c->tasks;
+    d.recs = c->recs;
+    d.task_off = c->task_off_dev;
+    d.n_tasks = c->n_tasks_dev;
+    d.scale = c->scale_dev;
+    d.split_partial = c->split_partial;
+    d.split_count = c->split_count;
+    d.I = static_cast<int32_t>(c->I);
+    d.J = static_cast<int32_t>(c->J);
+    d.K = c->K;
+    d.Kp = c->Kp;
+    d.nq = c->nq;
+    d.B = c->B;
+    d.lambda[0] = static_cast<float>(c->prior.lambda_w);
+    d.lambda[1] = static_cast<float>(c->prior.lambda_h);
+    d.inv_phi = static_cast<float>(1.0 / c->lik.phi);
+    d.beta = static_cast<float>(c->lik.beta);
+    d.mu_floor = static_cast<float>(c->opt.mu_floor);
+    d.seed_lo = static_cast<uint32_t>(c->opt.seed);
+    d.seed_hi = static_cast<uint32_t>(c->opt.seed >> 32);
+    d.mirror = c->prior.mirror ? 1 : 0;
+    d.prior_kind = c->prior.kind;
+    d.flags = c->opt.test_flags;
+    d.eps_tab = c->eps_tab - c->eps_base;
+    d.clock = c->clock;
+    d.cur_phase = (c->cur ^ static_cast<int>(c->t & 1)) & 1;
+    d.burn_in = static_cast<int32_t>(std::min<int64_t>(c->opt.burn_in, INT32_MAX));
+    d.thin = c->opt.thin;
+    d.has_heldout = c->n_ho > 0 ? 1 : 0;
+    for (int side = 0; side < 2; ++side) {
+        d.sum[side] = c->sum[side];
+        d.sum2[side] = c->sum2[side];
+    }
+    d.ho_ptr = c->ho_ptr;
+    d.ho_ent = c->ho_ent;
+    d.ho_sum = c->ho_sum;
+    d.nonfinite = c->nonfinite;
+    if (c->job_valid && std::memcmp(&d, &c->job_host, sizeof(d)) == 0) return PSGLD_OK;
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    if (!c->job_desc) {
+        std::vector<float> scl(c->B);
+        for (int32_t p = 0; p < c->B; ++p) scl[p] = part_scale(c, p);
+        psgld_status s = dev_alloc(c, &c->job_desc, 1);
+        if (!s) s = upload(c, &c->scale_dev, scl);
+        if (s) return s;
+        d.scale = c->scale_dev;
+    }
+    HIPTRY(c, hipMemcpy(c->job_desc, &d, sizeof(d), hipMemcpyHostToDevice));
+    c->job_host = d;
+    c->job_valid = true;
     return PSGLD_OK;
 }
 
@@ -790,6 +986,7 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     if (!c->loaded) return c->fail(PSGLD_E_STATE, "load training data first");
     if (c->heldout_loaded) return c->fail(PSGLD_E_STATE, "held-out cells already loaded");
     if (c->t > 0) return c->fail(PSGLD_E_STATE, "held-out cells must be loaded before the first step");
+    drop_graphs(c);
     if (n < 0 || n >= INT32_MAX) return c->fail(PSGLD_E_ARG, "n must be in [0, 2^31)");
     if (n > 0 && (!row || !col)) return c->fail(PSGLD_E_ARG, "row and col are required");
     psgld_status s;
@@ -916,10 +1113,111 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     if (n_iter < 0) return c->fail(PSGLD_E_ARG, "n_iter must be >= 0");
     if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
     if (c->t + n_iter >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
+    if (n_iter == 0) return PSGLD_OK;
     HIPTRY(c, hipSetDevice(c->opt.device));
-    for (int64_t it = 0; it < n_iter; ++it) {
-        if ((s = launch_iteration(c, c->t, sched, true))) return s;
-        c->t += 1;
+    if ((s = ensure_eps_table(c, sched, c->t, c->t + n_iter))) return s;
+    const int64_t L = graph_length(c);
+    while (n_iter > 0) {
+        if (L > 0 && n_iter >= L) {
+            hipGraphExec_t exec;
+            if ((s = get_graph(c, static_cast<int32_t>(c->t % c->B), c->cur, L, &exec))) return s;
+            if (c->clock_host != c->t) {
+                HIPTRY(c, launch_set_clock(c->clock, static_cast<int32_t>(c->t), c->stream));
+                c->clock_host = c->t;
+            }
+            HIPTRY(c, hipGraphLaunch(exec, c->stream));
+            c->clock_host += L;
+            for (int64_t k = 0; k < L; ++k) account_iteration(c, c->t + k);
+            c->cur ^= static_cast<int>(L & 1);
+            c->t += L;
+            n_iter -= L;
+        } else {
+            HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>(c->t % c->B), c->cur, nullptr,
+                                        static_cast<int32_t>(c->t), true, c->stream));
+            account_iteration(c, c->t);
+            c->cur ^= 1;
+            c->t += 1;
+            n_iter -= 1;
+        }
+    }
+    return PSGLD_OK;
+}
+
+psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *n_iter,
+                              const psgld_eps_schedule *scheds)
+{
+    if (n < 0 || (n > 0 && (!ctxs || !n_iter || !scheds))) return PSGLD_E_ARG;
+    if (n == 0) return PSGLD_OK;
+    for (int32_t j = 0; j < n; ++j) {
+        if (!ctxs[j]) return PSGLD_E_ARG;
+        for (int32_t m = 0; m < j; ++m)
+            if (ctxs[m] == ctxs[j]) return ctxs[j]->fail(PSGLD_E_ARG, "a context appears twice in the batch");
+    }
+    psgld_ctx *c0 = ctxs[0];
+    int64_t max_n = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        psgld_ctx *c = ctxs[j];
+        c->err.clear();
+        psgld_status s = check_schedule(c, &scheds[j]);
+        if (s) return s;
+        if (n_iter[j] < 0) return c->fail(PSGLD_E_ARG, "n_iter must be >= 0");
+        if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+        if (c->t + n_iter[j] >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
+        if (c->opt.device != c0->opt.device || c->stream != c0->stream)
+            return c->fail(PSGLD_E_ARG, "batched contexts must share one device and one stream");
+        max_n = std::max(max_n, n_iter[j]);
+    }
+    HIPTRY(c0, hipSetDevice(c0->opt.device));
+    hipStream_t stream = c0->stream;
+    std::vector<char> batched(n, 0);
+    for (int32_t j = 0; j < n; ++j) {
+        psgld_ctx *c = ctxs[j];
+        if (n_iter[j] == 0) continue;
+        psgld_status s = ensure_eps_table(c, &scheds[j], c->t, c->t + n_iter[j]);
+        if (s) return s;
+        batched[j] = c->dblocks_host.empty() ? 1 : 0;
+        if (!batched[j]) continue;
+        if ((s = sync_job_desc(c))) return s;
+        if (c->clock_host != c->t) {
+            HIPTRY(c, launch_set_clock(c->clock, static_cast<int32_t>(c->t), stream));
+            c->clock_host = c->t;
+        }
+    }
+    for (int64_t k = 0; k < max_n; ++k) {
+        // one launch per kernel variant (lanes per group, likelihood) and 64 contexts
+        std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+        std::vector<int32_t *> clocks;
+        for (int32_t j = 0; j < n; ++j)
+            if (k < n_iter[j] && batched[j]) {
+                groups[{ctxs[j]->lpg, ctxs[j]->lik_kind}].push_back(j);
+                clocks.push_back(ctxs[j]->clock);
+            }
+        for (auto &g : groups) {
+            const std::vector<int32_t> &js = g.second;
+            for (size_t first = 0; first < js.size(); first += kMaxBatch) {
+                BatchArgs b{};
+                b.n = static_cast<int32_t>(std::min<size_t>(kMaxBatch, js.size() - first));
+                b.wg_first[0] = 0;
+                for (int32_t q = 0; q < b.n; ++q) {
+                    psgld_ctx *c = ctxs[js[first + q]];
+                    b.jobs[q] = c->job_desc;
+                    b.wg_first[q + 1] = b.wg_first[q] + c->max_tasks;
+                }
+                HIPTRY(c0, launch_sparse_batch(b, g.first.second, g.first.first, stream));
+            }
+        }
+        if (!clocks.empty()) HIPTRY(c0, launch_advance_clocks(clocks.data(), static_cast<int>(clocks.size()), stream));
+        for (int32_t j = 0; j < n; ++j) {
+            if (k >= n_iter[j]) continue;
+            psgld_ctx *c = ctxs[j];
+            if (!batched[j])
+                HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>(c->t % c->B), c->cur, nullptr,
+                                            static_cast<int32_t>(c->t), true, stream));
+            account_iteration(c, c->t);
+            c->cur ^= 1;
+            c->t += 1;
+            if (batched[j]) c->clock_host = c->t;
+        }
     }
     return PSGLD_OK;
 }
@@ -940,6 +1238,7 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
         if ((s = check_schedule(c, sched))) return s;
         if ((s = sync_and_check(c))) return s;
         if (iters < 1) iters = c->B;
+        if ((s = ensure_eps_table(c, sched, c->t, c->t + iters))) return s;
         // trials run on copies of the state, from the context's current t
         const size_t nw = static_cast<size_t>(c->I) * c->Kp + kFactorPad, nh = static_cast<size_t>(c->J) * c->Kp + kFactorPad;
         const int cur0 = c->cur;
@@ -961,7 +1260,8 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
                 c->cur = cur0;
                 HIPTRY(c, hipEventRecord(e0, c->stream));
                 for (int32_t it = 0; it < iters; ++it)
-                    if ((s = launch_iteration(c, c->t + it, sched, false))) return s;
+                    HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>((c->t + it) % c->B), (cur0 + it) & 1,
+                                                nullptr, static_cast<int32_t>(c->t + it), false, c->stream));
                 HIPTRY(c, hipEventRecord(e1, c->stream));
                 HIPTRY(c, hipEventSynchronize(e1));
                 HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
@@ -1229,7 +1529,9 @@ void psgld_destroy(psgld_ctx *c)
     if (c->device_ready) {
         (void)hipSetDevice(c->opt.device);
         (void)hipStreamSynchronize(c->stream);
+        drop_graphs(c);
         for (void *p : c->allocs) (void)hipFree(p);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;

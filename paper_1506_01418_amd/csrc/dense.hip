@@ -66,14 +66,15 @@ __device__ __forceinline__ void mma16(v4f (&acc)[NACC], int nb, int kd, int lane
 
 // The Langevin step of four consecutive parameters k0..k0+3 of row `index`
 // of factor `side`, with gradient g of the scaled likelihood.
-__device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, int side, int index, int k0, const float xo[4],
+__device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, const IterScalars &it, int side, int index,
+                                               int k0, const float xo[4],
                                const float g[4])
 {
     const bool frozen = (a.flags & (side == 0 ? PSGLD_TEST_FREEZE_W : PSGLD_TEST_FREEZE_H)) != 0;
     const bool noisy = !frozen && !(a.flags & PSGLD_TEST_NOISE_OFF);
     float z[4] = {0.f, 0.f, 0.f, 0.f};
     if (noisy) {
-        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, a.t, static_cast<uint32_t>(side),
+        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, it.t, static_cast<uint32_t>(side),
                                    static_cast<uint32_t>(index), static_cast<uint32_t>(k0 / 4));
         z[0] = nz.z[0];
         z[1] = nz.z[1];
@@ -88,7 +89,7 @@ __device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, int side,
         float v = xo[c];
         if (!frozen) {
             const float pg = a.prior_kind == PSGLD_PRIOR_EXPONENTIAL ? (xo[c] >= 0.f ? -lam : lam) : -lam * xo[c];
-            v = xo[c] + a.eps * (a.scale * g[c] + pg) + a.sigma * z[c];
+            v = xo[c] + it.eps * (a.scale * g[c] + pg) + it.sigma * z[c];
             if (a.mirror) v = fabsf(v);
         }
         if (k0 + c >= a.K) v = 0.f;
@@ -97,8 +98,8 @@ __device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, int side,
     }
     const size_t off = static_cast<size_t>(index) * a.Kp + k0;
     *reinterpret_cast<float4 *>(a.x_new[side] + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
-    if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(a.t));
-    if (a.do_moments) {
+    if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(it.t));
+    if (it.do_moments) {
         double *s = a.sum[side] + off;
         double *s2 = a.sum2[side] + off;
 #pragma unroll
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
     extern __shared__ float lds[];
     const DenseTile tile = a.tiles[blockIdx.x];
     const DenseBlock blk = a.blocks[tile.block];
+    const IterScalars itr = iter_scalars(a.clk);
     const int m = blk.m, MT = (m + a.row_align - 1) / a.row_align * a.row_align;
     const int KS = a.KS, Kp = a.Kp;
     const int sw = KS + 1;            // odd row strides: no LDS bank conflicts
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
                         const uint8_t mk = M[cell];
                         if (mk == kMaskTrain)
                             e = tweedie_residual<LIK>(V[cell], acc[t][r], a.inv_phi, a.beta, a.mu_floor);
-                        else if (mk == kMaskHeld && a.do_heldout)
+                        else if (mk == kMaskHeld && itr.do_heldout)
                             e = acc[t][r];
                     }
                     sE[i * se + j] = e;
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
             }
         }
         __syncthreads();
-        if (a.do_heldout && tile.ho_end > tile.ho_begin) {
+        if (itr.do_heldout && tile.ho_end > tile.ho_begin) {
             // held-out cells of this sub-tile: add their mean, then zero them in E
             for (int h = tile.ho_begin + tid; h < tile.ho_end; h += kDenseThreads) {
                 const DenseHeld c = a.heldout[h];
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
                     const float g[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
                     const float xo[4] = {sH[j * sw + k0], sH[j * sw + k0 + 1], sH[j * sw + k0 + 2],
                                          sH[j * sw + k0 + 3]};
-                    dense_langevin(a, 1, col0 + j, k0, xo, g);
+                    dense_langevin(a, itr, 1, col0 + j, k0, xo, g);
                 }
             }
             // G_W^T += H^T E^T (k-tile kt x MT rows)
@@ -244,6 +246,7 @@ __global__ void dense_w_update_kernel(DenseIterArgs a)
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= blk.m * nq) return;
     const int i = w / nq, k0 = 4 * (w % nq);
+    const IterScalars it = iter_scalars(a.clk);
     // partials loaded eight at a time, added in partial order
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
     const float *base = a.w_partial + (static_cast<size_t>(blk.first_partial) * a.slot_rows + i) * a.Kp + k0;
@@ -265,7 +268,7 @@ __global__ void dense_w_update_kernel(DenseIterArgs a)
     const float *x = a.x_old[0] + static_cast<size_t>(blk.row0 + i) * a.Kp + k0;
     const float xo[4] = {x[0], x[1], x[2], x[3]};
     const float gr[4] = {g.x, g.y, g.z, g.w};
-    dense_langevin(a, 0, blk.row0 + i, k0, xo, gr);
+    dense_langevin(a, it, 0, blk.row0 + i, k0, xo, gr);
 }
 
 template <bool BF16>

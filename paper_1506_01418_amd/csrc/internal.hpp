@@ -55,6 +55,46 @@ struct GroupRec {
 };
 
 
+// Which global iteration a launch runs, and the scalars that depend on it.
+// Step sizes are computed on the host in FP64 (eps_t = a (t0 + t)^-gamma and
+// sqrt(2 eps_t), each rounded once to FP32) into a device table indexed by t;
+// a launch finds t as *clock + k, so a captured sequence of launches replays
+// for any starting iteration once the host has set the clock.
+struct IterClock {
+    const float2 *eps_tab;    // (eps_t, sigma_t) for t = 0 .. table length - 1
+    const int32_t *clock;     // device iteration counter, or null (t = k)
+    int32_t k;
+    int32_t burn_in, thin;    // moments at t >= burn_in with (t - burn_in) % thin == 0
+    int32_t bookkeeping;      // 0: no moments and no held-out sums (tuning trials)
+    int32_t has_heldout;
+};
+
+struct IterScalars {
+    uint32_t t;
+    float eps, sigma;
+    bool do_moments, do_heldout;
+};
+
+__device__ __forceinline__ IterScalars iter_scalars_at(int32_t t, const float2 *eps_tab, int32_t burn_in,
+                                                     int32_t thin, bool bookkeeping, bool has_heldout)
+{
+    IterScalars s;
+    const float2 es = eps_tab[t];
+    s.t = static_cast<uint32_t>(t);
+    s.eps = es.x;
+    s.sigma = es.y;
+    const bool post = bookkeeping && t >= burn_in;
+    s.do_moments = post && (t - burn_in) % thin == 0;
+    s.do_heldout = post && has_heldout;
+    return s;
+}
+
+__device__ __forceinline__ IterScalars iter_scalars(const IterClock &c)
+{
+    const int32_t t = (c.clock ? *c.clock : 0) + c.k;
+    return iter_scalars_at(t, c.eps_tab, c.burn_in, c.thin, c.bookkeeping != 0, c.has_heldout != 0);
+}
+
 // Arguments of one sparse iteration (one part), passed by value.
 struct SparseIterArgs {
     const float *x_old[2];   // [0] W (I x Kp), [1] H stored J x Kp
@@ -67,20 +107,65 @@ struct SparseIterArgs {
     float *split_partial;    // scratch: Kp floats per split share
     int32_t *split_count;    // arrival counters, one per split item (kept at 0 between launches)
     int32_t K, Kp, nq;
-    float eps, sigma, scale;
+    float scale;             // s_p = N / |part p|
     float lambda[2];
     float inv_phi, beta, mu_floor;
-    uint32_t seed_lo, seed_hi, t;
+    uint32_t seed_lo, seed_hi;
     int32_t mirror, prior_kind;
     uint32_t flags;          // PSGLD_TEST_* bits
-    int32_t do_moments;
+    IterClock clk;
     double *sum[2], *sum2[2];
-    int32_t do_heldout;
     const int32_t *ho_ptr;   // part's held-out row offsets (length I+1)
     const HeldEntry *ho_ent;
     double *ho_sum;
     int32_t *nonfinite;      // min iteration with a non-finite result
 };
+
+// A context as the batched kernel sees it: everything that stays fixed
+// between iterations, in device memory.  The iteration t comes from the
+// context's own clock; the part is t mod B, the buffer read is
+// (t + cur_phase) & 1, and the part's tables are indexed by the part.
+struct JobDesc {
+    float *W[2], *H[2];
+    const int32_t *rowptr, *colptr;   // part-major: B x I and B x J offsets (+1)
+    const Entry *ent[2];
+    const WgTask *tasks;
+    const GroupRec *recs;
+    const int32_t *task_off;          // per part: its first task
+    const int32_t *n_tasks;           // per part
+    const float *scale;               // per part: s_p
+    float *split_partial;
+    int32_t *split_count;
+    int32_t I, J, K, Kp, nq, B;
+    float lambda[2];
+    float inv_phi, beta, mu_floor;
+    uint32_t seed_lo, seed_hi;
+    int32_t mirror, prior_kind;
+    uint32_t flags;
+    const float2 *eps_tab;            // indexed by the global iteration
+    const int32_t *clock;
+    int32_t cur_phase;
+    int32_t burn_in, thin, has_heldout;
+    double *sum[2], *sum2[2];
+    const int32_t *ho_ptr;            // part-major, B x I (+1), or null
+    const HeldEntry *ho_ent;
+    double *ho_sum;
+    int32_t *nonfinite;
+};
+
+// One batched launch: up to kMaxBatch contexts of one kernel variant;
+// work-groups [wg_first[j], wg_first[j + 1]) serve context j (its largest
+// part's task count; work-groups past the current part's count exit).
+constexpr int kMaxBatch = 64;
+struct BatchArgs {
+    const JobDesc *jobs[kMaxBatch];
+    int32_t wg_first[kMaxBatch + 1];
+    int32_t n;
+};
+
+hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lanes_per_group, hipStream_t stream);
+// *clocks[j] += 1 for j < n.
+hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream);
 
 // Launches one sparse iteration with the kernel variant chosen for (K, lik).
 hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lanes_per_group,
@@ -160,15 +245,14 @@ struct DenseIterArgs {
     int32_t slot_rows;          // rows of every W partial slot (the largest padded block height)
     int32_t row_align;          // block heights are padded to this (16 FP32, 32 BF16)
     int32_t K, Kp, KS;          // KS = K rounded up to row_align
-    float eps, sigma, scale;
+    float scale;
     float lambda[2];
     float inv_phi, beta, mu_floor;
-    uint32_t seed_lo, seed_hi, t;
+    uint32_t seed_lo, seed_hi;
     int32_t mirror, prior_kind;
     uint32_t flags;
-    int32_t do_moments;
+    IterClock clk;              // has_heldout: dense blocks hold held-out cells
     double *sum[2], *sum2[2];
-    int32_t do_heldout;
     const DenseHeld *heldout;   // held-out cells of dense blocks, grouped by tile
     double *ho_sum;
     int32_t *nonfinite;
@@ -195,5 +279,8 @@ hipError_t launch_loglik(const float *W, const float *Hs, const int32_t *row_of_
                          const Entry *ent, int64_t n, int K, int Kp, double beta, double phi,
                          double mu_floor, double *partials, int n_blocks, hipStream_t stream);
 hipError_t launch_sum_in_order(const double *partials, int n, double *out, hipStream_t stream);
+// *clock = value, and *clock += delta, as kernels (so both can be captured).
+hipError_t launch_set_clock(int32_t *clock, int32_t value, hipStream_t stream);
+hipError_t launch_advance_clock(int32_t *clock, int32_t delta, hipStream_t stream);
 
 }  // namespace psgld

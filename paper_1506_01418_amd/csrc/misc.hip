@@ -45,6 +45,16 @@ __device__ double dbeta(double v, double mu, double beta)
            pow(mu, beta) / beta;
 }
 
+__global__ void set_clock_kernel(int32_t *clock, int32_t value)
+{
+    if (threadIdx.x == 0) *clock = value;
+}
+
+__global__ void advance_clock_kernel(int32_t *clock, int32_t delta)
+{
+    if (threadIdx.x == 0) *clock += delta;
+}
+
 constexpr int kLLThreads = 256;
 
 __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
@@ -154,6 +164,18 @@ hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock
 hipError_t launch_sum_in_order(const double *partials, int n, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(sum_in_order_kernel, dim3(1), dim3(64), 0, stream, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_clock(int32_t *clock, int32_t value, hipStream_t stream)
+{
+    hipLaunchKernelGGL(set_clock_kernel, dim3(1), dim3(64), 0, stream, clock, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_clock(int32_t *clock, int32_t delta, hipStream_t stream)
+{
+    hipLaunchKernelGGL(advance_clock_kernel, dim3(1), dim3(64), 0, stream, clock, delta);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@
 //  * the Langevin step, noise, prior and mirroring are applied by the item's
 //    lead group right after its gradient, into the other ping-pong buffer;
 //    the old buffers are only read, so no item waits for another.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "noise.hpp"
 
@@ -104,6 +106,14 @@ __device__ __forceinline__ float residual(float v, float mu, const SparseIterArg
 
 __device__ __forceinline__ float4 load4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
+// The side's member of a W/H pair, by selection rather than indexing, so an
+// argument block held in registers is never indexed dynamically.
+template <typename T>
+__device__ __forceinline__ T pick(int side, T w, T h)
+{
+    return side ? h : w;
+}
+
 // One group's view of its current item: the item's own row (x), and the
 // first batch of its entry records.
 struct ItemStart {
@@ -117,56 +127,64 @@ __device__ __forceinline__ ItemStart start_item(const SparseIterArgs &a, const W
     ItemStart st;
     st.x = make_float4(0.f, 0.f, 0.f, 0.f);
     if (rec.item >= 0 && qlane)
-        st.x = load4(a.x_old[task.side] + static_cast<size_t>(rec.item) * a.Kp + 4 * lane);
-    const Entry *ent = a.ent[task.side];
+        st.x = load4(pick(task.side, a.x_old[0], a.x_old[1]) + static_cast<size_t>(rec.item) * a.Kp + 4 * lane);
+    const Entry *ent = pick(task.side, a.ent[0], a.ent[1]);
     const int s0 = rec.item >= 0 ? rec.s0 : 0;
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) st.first[u] = ent[s0 + u];
     return st;
 }
 
-// Gradient of the likelihood over the group's entries [s0, s1).  Full
-// batches of kUnroll entries run without masks: lanes past ceil(K/4) have
-// x = 0, read one row ahead (the factor arrays are padded) and never store;
-// the next batch's entry records (arrays padded too) are fetched while the
-// current batch is reduced.  The tail runs one entry at a time.
+// Gradient of the likelihood over the group's entries [s0, s1), in batches
+// of kUnroll entries whose records are in registers before the batch starts
+// (the first batch from start_item, each next one fetched while the current
+// one is reduced).  Lanes past ceil(K/4) have x = 0 and read one row ahead
+// (the factor arrays are padded); a batch's records past s1 belong to the
+// next item or to the padding of the entry array, so their partner reads stay
+// in bounds and only their contributions are masked.  A short item is thus one
+// round of partner loads, not one per entry.
 template <int LPG, int LIK>
 __device__ __forceinline__ float4 item_gradient(const SparseIterArgs &a, const WgTask &task,
                                                 const GroupRec &rec, const ItemStart &st, int lane)
 {
     const float4 x = st.x;
-    const Entry *__restrict__ ent = a.ent[task.side];
-    const float *other_lane = a.x_old[task.side ^ 1] + 4 * lane;
+    const Entry *__restrict__ ent = pick(task.side, a.ent[0], a.ent[1]);
+    const float *other_lane = pick(task.side, a.x_old[1], a.x_old[0]) + 4 * lane;
     const int s0 = rec.s0, s1 = rec.item >= 0 ? rec.s1 : rec.s0;
     const int full_end = s0 + (s1 - s0) / kUnroll * kUnroll;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    Entry cur[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) cur[u] = st.first[u];
     int e = s0;
-    if (e < full_end) {
-        Entry cur[kUnroll];
+    for (; e < full_end; e += kUnroll) {
+        float4 o[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) cur[u] = st.first[u];
-        for (; e < full_end; e += kUnroll) {
-            float4 o[kUnroll];
+        for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
+        Entry nxt[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
-            Entry nxt[kUnroll];
+        for (int u = 0; u < kUnroll; ++u) nxt[u] = ent[e + kUnroll + u];
+        float mu[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) nxt[u] = ent[e + kUnroll + u];
-            float mu[kUnroll];
+        for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
+        group_sum_n<LPG, kUnroll>(mu);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
-            group_sum_n<LPG, kUnroll>(mu);
+        for (int u = 0; u < kUnroll; ++u) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
-        }
+        for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
     }
-    for (; e < s1; ++e) {
-        const Entry en = ent[e];
-        const float4 o = load4(other_lane + en.off);
-        const float mu = group_sum<LPG>(dot4(x, o));
-        axpy4(acc, residual<LIK>(en.val, mu, a), o);
+    const int n = s1 - e;   // 0 .. kUnroll - 1 entries left
+    if (n > 0) {
+        float4 o[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
+        float mu[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
+        group_sum_n<LPG, kUnroll>(mu);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (u < n) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
     }
     return acc;
 }
@@ -174,10 +192,10 @@ __device__ __forceinline__ float4 item_gradient(const SparseIterArgs &a, const W
 // Held-out sums, then the Langevin step of the item's k = 4 lane .. 4 lane + 3
 // with its full gradient g, by the item's lead group.
 template <int LPG>
-__device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, int item, float4 x,
-                                            float4 g, int lane, bool qlane)
+__device__ __forceinline__ void item_update(const SparseIterArgs &a, const IterScalars &it, int side, int item,
+                                            float4 x, float4 g, int lane, bool qlane)
 {
-    if (side == 0 && a.do_heldout) {
+    if (side == 0 && it.do_heldout) {
         const float *other_lane = a.x_old[1] + 4 * lane;
         const int hb = a.ho_ptr[item], he = a.ho_ptr[item + 1];
         for (int h = hb; h < he; ++h) {
@@ -191,7 +209,7 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, i
     const bool noisy = !frozen && !(a.flags & PSGLD_TEST_NOISE_OFF);
     float z[4] = {0.f, 0.f, 0.f, 0.f};
     if (noisy) {
-        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, a.t, static_cast<uint32_t>(side),
+        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, it.t, static_cast<uint32_t>(side),
                                    static_cast<uint32_t>(item), static_cast<uint32_t>(lane));
         z[0] = nz.z[0];
         z[1] = nz.z[1];
@@ -200,7 +218,7 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, i
     }
     const float xo[4] = {x.x, x.y, x.z, x.w};
     const float gr[4] = {g.x, g.y, g.z, g.w};
-    const float lam = a.lambda[side];
+    const float lam = pick(side, a.lambda[0], a.lambda[1]);
     float xn[4];
     bool finite = true;
 #pragma unroll
@@ -209,7 +227,7 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, i
         if (!frozen) {
             const float pg = a.prior_kind == PSGLD_PRIOR_EXPONENTIAL ? (xo[c] >= 0.f ? -lam : lam)
                                                                      : -lam * xo[c];
-            v = xo[c] + a.eps * (a.scale * gr[c] + pg) + a.sigma * z[c];
+            v = xo[c] + it.eps * (a.scale * gr[c] + pg) + it.sigma * z[c];
             if (a.mirror) v = fabsf(v);
         }
         if (4 * lane + c >= a.K) v = 0.f;
@@ -217,11 +235,11 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, i
         xn[c] = v;
     }
     const size_t off = static_cast<size_t>(item) * a.Kp + 4 * lane;
-    *reinterpret_cast<float4 *>(a.x_new[side] + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
-    if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(a.t));
-    if (a.do_moments) {
-        double2 *s = reinterpret_cast<double2 *>(a.sum[side] + off);
-        double2 *s2 = reinterpret_cast<double2 *>(a.sum2[side] + off);
+    *reinterpret_cast<float4 *>(pick(side, a.x_new[0], a.x_new[1]) + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+    if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(it.t));
+    if (it.do_moments) {
+        double2 *s = reinterpret_cast<double2 *>(pick(side, a.sum[0], a.sum[1]) + off);
+        double2 *s2 = reinterpret_cast<double2 *>(pick(side, a.sum2[0], a.sum2[1]) + off);
         const double d0 = xn[0], d1 = xn[1], d2 = xn[2], d3 = xn[3];
         double2 p0 = s[0], p1 = s[1], q0 = s2[0], q1 = s2[1];
         p0.x += d0;
@@ -239,11 +257,11 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, int side, i
     }
 }
 
-// One work-group per task.  The task's records, then each group's own row
-// and entries, then its partner rows are fetched; the item's lead group
-// applies the update.
+// One work-group's task t of the part.  The task's records, then each
+// group's own row and entries, then its partner rows are fetched; the item's
+// lead group applies the update.
 template <int LPG, int LIK>
-__global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterArgs a)
+__device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterScalars &it, int t)
 {
     constexpr int Q = kBlockThreads / LPG;
     __shared__ float4 partial[kBlockThreads];
@@ -253,7 +271,6 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterAr
     const int lane = tid % LPG;
     const bool qlane = lane < a.nq;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int t = blockIdx.x;
     const WgTask task = a.tasks[t];
     const GroupRec rec = a.recs[static_cast<size_t>(t) * Q + g];
     const ItemStart st = start_item(a, task, rec, lane, qlane);
@@ -313,7 +330,99 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterAr
         }
     }
 
-    if (lead) item_update<LPG>(a, task.side, rec.item, st.x, acc, lane, qlane);
+    if (lead) item_update<LPG>(a, it, task.side, rec.item, st.x, acc, lane, qlane);
+}
+
+// One work-group per task of the part.
+template <int LPG, int LIK>
+__global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterArgs a)
+{
+    sparse_task<LPG, LIK>(a, iter_scalars(a.clk), blockIdx.x);
+}
+
+// Several contexts in one launch: the work-group finds its context, reads
+// the context's clock, and runs task (blockIdx - first) of the current part
+// with exactly the arguments a single-context launch would pass.
+template <int LPG, int LIK>
+__global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b)
+{
+    const int wg = blockIdx.x;
+    int lo = 0, hi = b.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b.wg_first[mid] <= wg) lo = mid;
+        else hi = mid;
+    }
+    const JobDesc &d = *b.jobs[lo];
+    const int32_t t = *d.clock;
+    const int p = t % d.B;
+    const int task = wg - b.wg_first[lo];
+    if (task >= d.n_tasks[p]) return;
+    const int cur = (t + d.cur_phase) & 1;
+    constexpr int Q = kBlockThreads / LPG;
+    SparseIterArgs a;
+    a.x_old[0] = d.W[cur];
+    a.x_old[1] = d.H[cur];
+    a.x_new[0] = d.W[cur ^ 1];
+    a.x_new[1] = d.H[cur ^ 1];
+    a.ptr[0] = d.rowptr + static_cast<size_t>(p) * d.I;
+    a.ptr[1] = d.colptr + static_cast<size_t>(p) * d.J;
+    a.ent[0] = d.ent[0];
+    a.ent[1] = d.ent[1];
+    a.tasks = d.tasks + d.task_off[p];
+    a.recs = d.recs + static_cast<size_t>(d.task_off[p]) * Q;
+    a.n_tasks = d.n_tasks[p];
+    a.split_partial = d.split_partial;
+    a.split_count = d.split_count;
+    a.K = d.K;
+    a.Kp = d.Kp;
+    a.nq = d.nq;
+    a.scale = d.scale[p];
+    a.lambda[0] = d.lambda[0];
+    a.lambda[1] = d.lambda[1];
+    a.inv_phi = d.inv_phi;
+    a.beta = d.beta;
+    a.mu_floor = d.mu_floor;
+    a.seed_lo = d.seed_lo;
+    a.seed_hi = d.seed_hi;
+    a.mirror = d.mirror;
+    a.prior_kind = d.prior_kind;
+    a.flags = d.flags;
+    a.clk = IterClock{};
+    a.sum[0] = d.sum[0];
+    a.sum[1] = d.sum[1];
+    a.sum2[0] = d.sum2[0];
+    a.sum2[1] = d.sum2[1];
+    a.ho_ptr = d.ho_ptr ? d.ho_ptr + static_cast<size_t>(p) * d.I : nullptr;
+    a.ho_ent = d.ho_ent;
+    a.ho_sum = d.ho_sum;
+    a.nonfinite = d.nonfinite;
+    const IterScalars it = iter_scalars_at(t, d.eps_tab, d.burn_in, d.thin, true, d.has_heldout != 0);
+    sparse_task<LPG, LIK>(a, it, task);
+}
+
+struct ClockList {
+    int32_t *clocks[kMaxBatch];
+    int32_t n;
+};
+
+__global__ void advance_clocks_kernel(ClockList l)
+{
+    if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += 1;
+}
+
+template <int LPG>
+hipError_t launch_batch_lpg(const BatchArgs &b, int lik, hipStream_t stream)
+{
+    const dim3 grid(static_cast<unsigned>(b.wg_first[b.n])), block(kBlockThreads);
+    switch (lik) {
+    case LIK_GAUSS: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GAUSS>), grid, block, 0, stream, b); break;
+    case LIK_POISSON: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_POISSON>), grid, block, 0, stream, b); break;
+    case LIK_HALF: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_HALF>), grid, block, 0, stream, b); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GAMMA>), grid, block, 0, stream, b); break;
+    default: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GENERAL>), grid, block, 0, stream, b); break;
+    }
+    return hipGetLastError();
 }
 
 template <int LPG>
@@ -341,6 +450,34 @@ int sparse_threads_per_group(int K)
     int lpg = 1;
     while (lpg < nq) lpg *= 2;
     return lpg;
+}
+
+hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, hipStream_t stream)
+{
+    if (b.n <= 0 || b.n > kMaxBatch || b.wg_first[b.n] == 0) return b.n > kMaxBatch ? hipErrorInvalidValue : hipSuccess;
+    switch (lpg) {
+    case 1: return launch_batch_lpg<1>(b, lik, stream);
+    case 2: return launch_batch_lpg<2>(b, lik, stream);
+    case 4: return launch_batch_lpg<4>(b, lik, stream);
+    case 8: return launch_batch_lpg<8>(b, lik, stream);
+    case 16: return launch_batch_lpg<16>(b, lik, stream);
+    case 32: return launch_batch_lpg<32>(b, lik, stream);
+    case 64: return launch_batch_lpg<64>(b, lik, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream)
+{
+    for (int first = 0; first < n; first += kMaxBatch) {
+        ClockList l{};
+        l.n = std::min(kMaxBatch, n - first);
+        for (int j = 0; j < l.n; ++j) l.clocks[j] = clocks[first + j];
+        hipLaunchKernelGGL(advance_clocks_kernel, dim3(1), dim3(kMaxBatch), 0, stream, l);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lpg, hipStream_t stream)

@@ -13,7 +13,8 @@ available, so synthetic stand-ins of the same shape and value range are used:
     (stands in for MovieLens 10M, Section 4.3).
   * ``dense_tweedie``   -- spectrogram-shaped non-negative matrix with
     compound Poisson-gamma (Tweedie, beta = 0.5) noise (Sections 4.2.1-4.2.2).
-  * ``job_stream``      -- a stream of mixed-size factorisation jobs.
+  * ``serving_job``     -- one job of a stream of mixed-size factorisation
+    jobs, with ``job_arrivals`` giving Poisson arrival times.
 """
 from __future__ import annotations
 
@@ -309,3 +310,64 @@ def to_dense(wl: Workload):
     V[wl.hrow, wl.hcol] = wl.hval
     mask[wl.row, wl.col] = 1
     return V, mask
+
+
+def serving_job(j, seed0=5000, T=500, burn_in=250, thin=10, heldout=0.1, max_side=4096, name="serving_job"):
+    """Job j of the serving stream: I, J log-uniform on [64, max_side], observed
+    density log-uniform on [0.01, 1] (uniform support), K from {8, 16, 32, 64},
+    and either Poisson NMF data (Gamma(1, 1) factors of rank K, v ~ Poisson,
+    fit with beta = 1, exponential priors, mirroring) or Gaussian data (rank-K
+    Gaussian factors with w.h of mean 3.5 and sd 1, v = w.h + N(0, 0.5^2),
+    fit with beta = 2, phi = 0.25, Gaussian priors).  B = clamp(min(I, J) //
+    128, 1, 32).  Dense jobs (density > 0.3) carry V and the training mask."""
+    rng = np.random.default_rng(seed0 + j)
+    lo, hi = np.log(64.0), np.log(float(max_side))
+    I = int(round(np.exp(rng.uniform(lo, hi))))
+    J = int(round(np.exp(rng.uniform(lo, hi))))
+    rho = float(np.exp(rng.uniform(np.log(0.01), 0.0)))
+    K = int(rng.choice([8, 16, 32, 64]))
+    poisson = bool(rng.integers(0, 2))
+    B = int(min(32, max(1, min(I, J) // 128)))
+    cells = I * J
+    n_obs = max(2, int(round(rho * cells)))
+    keys = np.sort(rng.choice(cells, size=n_obs, replace=False))
+    if poisson:
+        Wt = rng.gamma(1.0, 1.0, (I, K)).astype(np.float32)
+        Ht = rng.gamma(1.0, 1.0, (K, J)).astype(np.float32)
+    else:
+        m, s2 = gaussian_factor_moments(K)
+        Wt = (m + np.sqrt(s2) * rng.standard_normal((I, K))).astype(np.float32)
+        Ht = (m + np.sqrt(s2) * rng.standard_normal((K, J))).astype(np.float32)
+    mu = (Wt @ Ht).reshape(-1)[keys].astype(np.float64)
+    if poisson:
+        v = rng.poisson(mu).astype(np.float32)
+        beta, phi, prior, mirror = 1.0, 1.0, "exponential", True
+    else:
+        v = (mu + 0.5 * rng.standard_normal(len(mu))).astype(np.float32)
+        beta, phi, prior, mirror = 2.0, 0.25, "gaussian", False
+    tr, ho = _split_heldout(rng, n_obs, heldout)
+    rk, ck = (keys // J).astype(np.int32), (keys % J).astype(np.int32)
+    row, col, val = rk[tr], ck[tr], v[tr]
+    hrow, hcol, hval = rk[ho], ck[ho], v[ho]
+    a = step_scale(row, col, val, I, J, beta, phi)
+    W0, H0 = init_factors(np.random.default_rng(seed0 + 10_000 + j), I, J, K,
+                          float(val.mean()) if len(val) else 1.0, mirror)
+    dense = mask = None
+    if rho > 0.3:
+        dense = np.zeros((I, J), dtype=np.float32)
+        mask = np.zeros((I, J), dtype=np.uint8)
+        dense[row, col] = val
+        dense[hrow, hcol] = hval
+        mask[row, col] = 1
+    return Workload(f"{name}_{j}", I, J, K, B, beta, phi, prior, 1.0, 1.0, mirror,
+                    a, 1.0, 0.51, seed0 + 20_000 + j, T, burn_in, thin,
+                    row, col, val, hrow, hcol, hval, W0, H0, dense=dense, mask=mask,
+                    meta=dict(density=rho, poisson=poisson))
+
+
+def job_arrivals(n_jobs, rate=20.0, seed=3005):
+    """Arrival times (seconds) of a Poisson process of the given rate; rate
+    0 means every job arrives at time 0."""
+    if rate <= 0:
+        return np.zeros(n_jobs)
+    return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, n_jobs))
