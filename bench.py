@@ -114,6 +114,11 @@ def make_workload(name):
         wl = workloads.sparse_ratings()
         wl.thin = 10
         return wl
+    if name == "sparse_ratings_480k":
+        wl = workloads.sparse_ratings(I=480_000, J=17_800, nnz=100_000_000, K_true=30, K=100, B=64,
+                                      zipf_a=1.1, data_seed=1004, chain_seed=2004, name=name)
+        wl.thin = 10
+        return wl
     if name == "dense_poisson_256":
         return workloads.dense_poisson()
     if name == "sparse_ratings_small":
@@ -215,6 +220,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
                     help="operand precision of the dense-block kernels")
+    ap.add_argument("--entries-per-group", type=int, default=0,
+                    help="fix the sparse schedule's entries per group instead of tuning it")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one 256 MiB device-to-device copy kernel (torch), the reference "
+                         "for scaling HBM traffic counters")
     ap.add_argument("--jobs", type=int, default=200, help="serve_c5: number of jobs")
     ap.add_argument("--rate", type=float, default=20.0, help="serve_c5: arrivals per second (0: all at once)")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serve_c5: HBM budget of the running jobs")
@@ -248,7 +258,8 @@ def main():
     chosen = None
     if not dense:
         t_tune = time.perf_counter()
-        chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
+        cands = (args.entries_per_group,) if args.entries_per_group > 0 else (16, 32, 64, 128)
+        chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=cands, iters=wl.B)
         print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
               file=sys.stderr, flush=True)
     n_p, N = s.part_sizes()
@@ -335,6 +346,14 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 268435456 bytes read and written", file=sys.stderr, flush=True)
 
 
 def pkg_pieces(wl, which):

@@ -51,7 +51,7 @@ bool is_gfx950(int device)
 
 struct psgld_ctx {
     int64_t I = 0, J = 0;
-    int32_t K = 0, B = 0, Kp = 0, nq = 0, lpg = 0;
+    int32_t K = 0, B = 0, Kp = 0, nq = 0, lpg = 0, qpl = 1;
     psgld_likelihood lik{};
     psgld_prior prior{};
     psgld_options opt{};
@@ -564,7 +564,7 @@ hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *cl
     a.ho_ent = c->ho_ent;
     a.ho_sum = c->ho_sum;
     a.nonfinite = c->nonfinite;
-    hipError_t e = launch_sparse_iter(a, c->lik_kind, c->lpg, stream);
+    hipError_t e = launch_sparse_iter(a, c->lik_kind, c->lpg, c->qpl, stream);
     if (e != hipSuccess) return e;
     if (!c->dblocks_host.empty() && c->dblk_cnt[p] > 0) {
         DenseIterArgs d{};
@@ -795,6 +795,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     c->Kp = (K + 3) / 4 * 4;
     c->nq = (K + 3) / 4;
     c->lpg = sparse_threads_per_group(K);
+    c->qpl = sparse_quads_per_lane(K);
     c->lik = *lik;
     c->prior = *prior;
     c->opt = o;
@@ -1184,12 +1185,13 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
         }
     }
     for (int64_t k = 0; k < max_n; ++k) {
-        // one launch per kernel variant (lanes per group, likelihood) and 64 contexts
-        std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+        // one launch per kernel variant (lanes per group, quads per lane,
+        // likelihood) and 64 contexts
+        std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
         std::vector<int32_t *> clocks;
         for (int32_t j = 0; j < n; ++j)
             if (k < n_iter[j] && batched[j]) {
-                groups[{ctxs[j]->lpg, ctxs[j]->lik_kind}].push_back(j);
+                groups[std::make_tuple(ctxs[j]->lpg, ctxs[j]->qpl, ctxs[j]->lik_kind)].push_back(j);
                 clocks.push_back(ctxs[j]->clock);
             }
         for (auto &g : groups) {
@@ -1203,7 +1205,7 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
                     b.jobs[q] = c->job_desc;
                     b.wg_first[q + 1] = b.wg_first[q] + c->max_tasks;
                 }
-                HIPTRY(c0, launch_sparse_batch(b, g.first.second, g.first.first, stream));
+                HIPTRY(c0, launch_sparse_batch(b, std::get<2>(g.first), std::get<0>(g.first), std::get<1>(g.first), stream));
             }
         }
         if (!clocks.empty()) HIPTRY(c0, launch_advance_clocks(clocks.data(), static_cast<int>(clocks.size()), stream));

@@ -163,14 +163,16 @@ struct BatchArgs {
     int32_t n;
 };
 
-hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lanes_per_group, hipStream_t stream);
+hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lanes_per_group, int quads_per_lane,
+                               hipStream_t stream);
 // *clocks[j] += 1 for j < n.
 hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream);
 
 // Launches one sparse iteration with the kernel variant chosen for (K, lik).
-hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lanes_per_group,
+hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lanes_per_group, int quads_per_lane,
                               hipStream_t stream);
 int sparse_threads_per_group(int K);
+int sparse_quads_per_lane(int K);
 int sparse_block_threads();
 
 // Tunable shape of the sparse schedule (chosen per context by psgld_tune).

@@ -45,19 +45,12 @@ struct Job {
     std::string err;
 };
 
-int lanes_per_group(int32_t K)
-{
-    int l = 1;
-    while (l < (K + 3) / 4) l *= 2;
-    return l;
-}
-
 // Upper estimate of the device bytes of a job's context (every allocation
 // of the load, held-out and stepping calls, by the sizes they are made with).
 int64_t estimate_bytes(const psgld_job &j)
 {
     const int64_t I = j.I, J = j.J, B = j.B, Kp = (j.K + 3) / 4 * 4;
-    const int64_t Q = sparse_block_threads() / lanes_per_group(j.K);
+    const int64_t Q = sparse_block_threads() / sparse_threads_per_group(j.K);
     int64_t qlog = 0;
     while ((int64_t{1} << qlog) < Q) ++qlog;
     int64_t nnz = j.nnz;

@@ -28,7 +28,6 @@ namespace psgld {
 namespace {
 
 constexpr int kBlockThreads = 256;
-constexpr int kUnroll = 8;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
@@ -114,177 +113,226 @@ __device__ __forceinline__ T pick(int side, T w, T h)
     return side ? h : w;
 }
 
-// One group's view of its current item: the item's own row (x), and the
-// first batch of its entry records.
+// Entries per batch: a batch's partner loads are QPL float4 per lane each,
+// so the batch holds 8 / QPL entries (32 partner registers either way).
+template <int QPL>
+constexpr int kBatch = 8 / QPL;
+
+// Quad m of a lane: k = 4 (lane + m LPG) .. + 3, so consecutive lanes read
+// consecutive 16-byte pieces of a row.
+template <int LPG>
+__device__ __forceinline__ int quad_of(int lane, int m)
+{
+    return lane + m * LPG;
+}
+
+// One group's view of its current item: the lane's quads of the item's own
+// row (x), and the first batch of its entry records.
+template <int QPL>
 struct ItemStart {
-    float4 x;
-    Entry first[kUnroll];
+    float4 x[QPL];
+    Entry first[kBatch<QPL>];
 };
 
-__device__ __forceinline__ ItemStart start_item(const SparseIterArgs &a, const WgTask &task,
-                                                const GroupRec &rec, int lane, bool qlane)
+template <int LPG, int QPL>
+__device__ __forceinline__ ItemStart<QPL> start_item(const SparseIterArgs &a, const WgTask &task,
+                                                     const GroupRec &rec, int lane)
 {
-    ItemStart st;
-    st.x = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (rec.item >= 0 && qlane)
-        st.x = load4(pick(task.side, a.x_old[0], a.x_old[1]) + static_cast<size_t>(rec.item) * a.Kp + 4 * lane);
+    ItemStart<QPL> st;
+    const float *row = pick(task.side, a.x_old[0], a.x_old[1]) + static_cast<size_t>(rec.item) * a.Kp;
+#pragma unroll
+    for (int m = 0; m < QPL; ++m) {
+        const int q = quad_of<LPG>(lane, m);
+        st.x[m] = (rec.item >= 0 && q < a.nq) ? load4(row + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     const Entry *ent = pick(task.side, a.ent[0], a.ent[1]);
     const int s0 = rec.item >= 0 ? rec.s0 : 0;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) st.first[u] = ent[s0 + u];
+    for (int u = 0; u < kBatch<QPL>; ++u) st.first[u] = ent[s0 + u];
     return st;
 }
 
 // Gradient of the likelihood over the group's entries [s0, s1), in batches
-// of kUnroll entries whose records are in registers before the batch starts
+// of kBatch entries whose records are in registers before the batch starts
 // (the first batch from start_item, each next one fetched while the current
-// one is reduced).  Lanes past ceil(K/4) have x = 0 and read one row ahead
-// (the factor arrays are padded); a batch's records past s1 belong to the
-// next item or to the padding of the entry array, so their partner reads stay
-// in bounds and only their contributions are masked.  A short item is thus one
-// round of partner loads, not one per entry.
-template <int LPG, int LIK>
-__device__ __forceinline__ float4 item_gradient(const SparseIterArgs &a, const WgTask &task,
-                                                const GroupRec &rec, const ItemStart &st, int lane)
+// one is reduced).  Quads past ceil(K/4) have x = 0 and read up to one row
+// ahead (the factor arrays are padded and zero-initialised); a batch's
+// records past s1 belong to the next item or to the padding of the entry
+// array, so their partner reads stay in bounds and only their contributions
+// are masked.  A short item is thus one round of partner loads.
+template <int LPG, int QPL, int LIK>
+__device__ __forceinline__ void item_gradient(const SparseIterArgs &a, const WgTask &task, const GroupRec &rec,
+                                              const ItemStart<QPL> &st, int lane, float4 (&acc)[QPL])
 {
-    const float4 x = st.x;
+    constexpr int U = kBatch<QPL>;
     const Entry *__restrict__ ent = pick(task.side, a.ent[0], a.ent[1]);
     const float *other_lane = pick(task.side, a.x_old[1], a.x_old[0]) + 4 * lane;
     const int s0 = rec.s0, s1 = rec.item >= 0 ? rec.s1 : rec.s0;
-    const int full_end = s0 + (s1 - s0) / kUnroll * kUnroll;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    Entry cur[kUnroll];
+    const int full_end = s0 + (s1 - s0) / U * U;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) cur[u] = st.first[u];
+    for (int m = 0; m < QPL; ++m) acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    Entry cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = st.first[u];
     int e = s0;
-    for (; e < full_end; e += kUnroll) {
-        float4 o[kUnroll];
+    for (; e < full_end; e += U) {
+        float4 o[U][QPL];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
-        Entry nxt[kUnroll];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) nxt[u] = ent[e + kUnroll + u];
-        float mu[kUnroll];
+            for (int m = 0; m < QPL; ++m) o[u][m] = load4(other_lane + cur[u].off + 4 * m * LPG);
+        Entry nxt[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
-        group_sum_n<LPG, kUnroll>(mu);
+        for (int u = 0; u < U; ++u) nxt[u] = ent[e + U + u];
+        float mu[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
+        for (int u = 0; u < U; ++u) {
+            mu[u] = dot4(st.x[0], o[u][0]);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
+            for (int m = 1; m < QPL; ++m) mu[u] += dot4(st.x[m], o[u][m]);
+        }
+        group_sum_n<LPG, U>(mu);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float r = residual<LIK>(cur[u].val, mu[u], a);
+#pragma unroll
+            for (int m = 0; m < QPL; ++m) axpy4(acc[m], r, o[u][m]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
-    const int n = s1 - e;   // 0 .. kUnroll - 1 entries left
+    const int n = s1 - e;   // 0 .. U - 1 entries left
     if (n > 0) {
-        float4 o[kUnroll];
+        float4 o[U][QPL];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) o[u] = load4(other_lane + cur[u].off);
-        float mu[kUnroll];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) mu[u] = dot4(x, o[u]);
-        group_sum_n<LPG, kUnroll>(mu);
+            for (int m = 0; m < QPL; ++m) o[u][m] = load4(other_lane + cur[u].off + 4 * m * LPG);
+        float mu[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (u < n) axpy4(acc, residual<LIK>(cur[u].val, mu[u], a), o[u]);
+        for (int u = 0; u < U; ++u) {
+            mu[u] = dot4(st.x[0], o[u][0]);
+#pragma unroll
+            for (int m = 1; m < QPL; ++m) mu[u] += dot4(st.x[m], o[u][m]);
+        }
+        group_sum_n<LPG, U>(mu);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (u < n) {
+                const float r = residual<LIK>(cur[u].val, mu[u], a);
+#pragma unroll
+                for (int m = 0; m < QPL; ++m) axpy4(acc[m], r, o[u][m]);
+            }
     }
-    return acc;
 }
 
-// Held-out sums, then the Langevin step of the item's k = 4 lane .. 4 lane + 3
-// with its full gradient g, by the item's lead group.
-template <int LPG>
+// Held-out sums, then the Langevin step of the lane's quads with the full
+// gradient g, by the item's lead group.
+template <int LPG, int QPL>
 __device__ __forceinline__ void item_update(const SparseIterArgs &a, const IterScalars &it, int side, int item,
-                                            float4 x, float4 g, int lane, bool qlane)
+                                            const float4 (&x)[QPL], const float4 (&g)[QPL], int lane)
 {
     if (side == 0 && it.do_heldout) {
         const float *other_lane = a.x_old[1] + 4 * lane;
         const int hb = a.ho_ptr[item], he = a.ho_ptr[item + 1];
         for (int h = hb; h < he; ++h) {
             const HeldEntry c = a.ho_ent[h];
-            const float mu = group_sum<LPG>(dot4(x, load4(other_lane + c.off)));
+            float d = dot4(x[0], load4(other_lane + c.off));
+#pragma unroll
+            for (int m = 1; m < QPL; ++m) d += dot4(x[m], load4(other_lane + c.off + 4 * m * LPG));
+            const float mu = group_sum<LPG>(d);
             if (lane == 0) a.ho_sum[c.slot] += static_cast<double>(mu);
         }
     }
-    if (!qlane) return;
     const bool frozen = (a.flags & (side == 0 ? PSGLD_TEST_FREEZE_W : PSGLD_TEST_FREEZE_H)) != 0;
     const bool noisy = !frozen && !(a.flags & PSGLD_TEST_NOISE_OFF);
-    float z[4] = {0.f, 0.f, 0.f, 0.f};
-    if (noisy) {
-        const Normal4 nz = normal4(a.seed_lo, a.seed_hi, it.t, static_cast<uint32_t>(side),
-                                   static_cast<uint32_t>(item), static_cast<uint32_t>(lane));
-        z[0] = nz.z[0];
-        z[1] = nz.z[1];
-        z[2] = nz.z[2];
-        z[3] = nz.z[3];
-    }
-    const float xo[4] = {x.x, x.y, x.z, x.w};
-    const float gr[4] = {g.x, g.y, g.z, g.w};
     const float lam = pick(side, a.lambda[0], a.lambda[1]);
-    float xn[4];
+    float *xnew = pick(side, a.x_new[0], a.x_new[1]);
     bool finite = true;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        float v = xo[c];
-        if (!frozen) {
-            const float pg = a.prior_kind == PSGLD_PRIOR_EXPONENTIAL ? (xo[c] >= 0.f ? -lam : lam)
-                                                                     : -lam * xo[c];
-            v = xo[c] + it.eps * (a.scale * gr[c] + pg) + it.sigma * z[c];
-            if (a.mirror) v = fabsf(v);
+    for (int m = 0; m < QPL; ++m) {
+        const int q = quad_of<LPG>(lane, m);
+        if (q >= a.nq) continue;
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        if (noisy) {
+            const Normal4 nz = normal4(a.seed_lo, a.seed_hi, it.t, static_cast<uint32_t>(side),
+                                       static_cast<uint32_t>(item), static_cast<uint32_t>(q));
+            z[0] = nz.z[0];
+            z[1] = nz.z[1];
+            z[2] = nz.z[2];
+            z[3] = nz.z[3];
         }
-        if (4 * lane + c >= a.K) v = 0.f;
-        finite = finite && isfinite(v);
-        xn[c] = v;
+        const float xo[4] = {x[m].x, x[m].y, x[m].z, x[m].w};
+        const float gr[4] = {g[m].x, g[m].y, g[m].z, g[m].w};
+        float xn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float v = xo[c];
+            if (!frozen) {
+                const float pg = a.prior_kind == PSGLD_PRIOR_EXPONENTIAL ? (xo[c] >= 0.f ? -lam : lam)
+                                                                         : -lam * xo[c];
+                v = xo[c] + it.eps * (a.scale * gr[c] + pg) + it.sigma * z[c];
+                if (a.mirror) v = fabsf(v);
+            }
+            if (4 * q + c >= a.K) v = 0.f;
+            finite = finite && isfinite(v);
+            xn[c] = v;
+        }
+        const size_t off = static_cast<size_t>(item) * a.Kp + 4 * q;
+        *reinterpret_cast<float4 *>(xnew + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        if (it.do_moments) {
+            double2 *s = reinterpret_cast<double2 *>(pick(side, a.sum[0], a.sum[1]) + off);
+            double2 *s2 = reinterpret_cast<double2 *>(pick(side, a.sum2[0], a.sum2[1]) + off);
+            const double d0 = xn[0], d1 = xn[1], d2 = xn[2], d3 = xn[3];
+            double2 p0 = s[0], p1 = s[1], q0 = s2[0], q1 = s2[1];
+            p0.x += d0;
+            p0.y += d1;
+            p1.x += d2;
+            p1.y += d3;
+            q0.x += d0 * d0;
+            q0.y += d1 * d1;
+            q1.x += d2 * d2;
+            q1.y += d3 * d3;
+            s[0] = p0;
+            s[1] = p1;
+            s2[0] = q0;
+            s2[1] = q1;
+        }
     }
-    const size_t off = static_cast<size_t>(item) * a.Kp + 4 * lane;
-    *reinterpret_cast<float4 *>(pick(side, a.x_new[0], a.x_new[1]) + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
     if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(it.t));
-    if (it.do_moments) {
-        double2 *s = reinterpret_cast<double2 *>(pick(side, a.sum[0], a.sum[1]) + off);
-        double2 *s2 = reinterpret_cast<double2 *>(pick(side, a.sum2[0], a.sum2[1]) + off);
-        const double d0 = xn[0], d1 = xn[1], d2 = xn[2], d3 = xn[3];
-        double2 p0 = s[0], p1 = s[1], q0 = s2[0], q1 = s2[1];
-        p0.x += d0;
-        p0.y += d1;
-        p1.x += d2;
-        p1.y += d3;
-        q0.x += d0 * d0;
-        q0.y += d1 * d1;
-        q1.x += d2 * d2;
-        q1.y += d3 * d3;
-        s[0] = p0;
-        s[1] = p1;
-        s2[0] = q0;
-        s2[1] = q1;
-    }
 }
 
 // One work-group's task t of the part.  The task's records, then each
 // group's own row and entries, then its partner rows are fetched; the item's
 // lead group applies the update.
-template <int LPG, int LIK>
+template <int LPG, int QPL, int LIK>
 __device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterScalars &it, int t)
 {
     constexpr int Q = kBlockThreads / LPG;
-    __shared__ float4 partial[kBlockThreads];
+    __shared__ float4 partial[QPL][kBlockThreads];
     __shared__ int is_last;
     const int tid = threadIdx.x;
     const int g = tid / LPG;
     const int lane = tid % LPG;
-    const bool qlane = lane < a.nq;
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const WgTask task = a.tasks[t];
     const GroupRec rec = a.recs[static_cast<size_t>(t) * Q + g];
-    const ItemStart st = start_item(a, task, rec, lane, qlane);
+    const ItemStart<QPL> st = start_item<LPG, QPL>(a, task, rec, lane);
     const int G = 1 << task.glog2;
     const int sub = g & (G - 1);
-    float4 acc = item_gradient<LPG, LIK>(a, task, rec, st, lane);
+    float4 acc[QPL];
+    item_gradient<LPG, QPL, LIK>(a, task, rec, st, lane, acc);
 
     // Items split over G groups: combine the partial sums in a fixed order.
     if (G > 1) {
-        partial[tid] = acc;
+#pragma unroll
+        for (int m = 0; m < QPL; ++m) partial[m][tid] = acc[m];
         __syncthreads();
         if (sub == 0) {
-            acc = zero;
-            for (int s = 0; s < G; ++s) add4(acc, partial[(g + s) * LPG + lane]);
+#pragma unroll
+            for (int m = 0; m < QPL; ++m) {
+                acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int s = 0; s < G; ++s) add4(acc[m], partial[m][(g + s) * LPG + lane]);
+            }
         }
     }
     // Items split over work-groups: publish this share; the last share to
@@ -296,12 +344,17 @@ __device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterS
     // by the last share, after its count shows every other arrival.
     bool lead = rec.item >= 0 && rec.lead;
     if (task.n_split > 0) {
-        float *slot = a.split_partial + static_cast<size_t>(task.split_first + task.split_idx) * a.Kp + 4 * lane;
-        if (g == 0 && qlane) {
-            __hip_atomic_store(slot + 0, acc.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(slot + 1, acc.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(slot + 2, acc.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(slot + 3, acc.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        float *slot = a.split_partial + static_cast<size_t>(task.split_first + task.split_idx) * a.Kp;
+        if (g == 0) {
+#pragma unroll
+            for (int m = 0; m < QPL; ++m) {
+                const int q = quad_of<LPG>(lane, m);
+                if (q >= a.nq) continue;
+                __hip_atomic_store(slot + 4 * q + 0, acc[m].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(slot + 4 * q + 1, acc[m].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(slot + 4 * q + 2, acc[m].z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(slot + 4 * q + 3, acc[m].w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the stores are complete
         __syncthreads();
@@ -314,15 +367,20 @@ __device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterS
         }
         __syncthreads();
         if (is_last) {
-            if (g == 0 && qlane) {
-                acc = zero;
-                const float *first = a.split_partial + static_cast<size_t>(task.split_first) * a.Kp + 4 * lane;
-                for (int s = 0; s < task.n_split; ++s) {
-                    const float *q = first + static_cast<size_t>(s) * a.Kp;
-                    acc.x += __hip_atomic_load(q + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    acc.y += __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    acc.z += __hip_atomic_load(q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    acc.w += __hip_atomic_load(q + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (g == 0) {
+                const float *first = a.split_partial + static_cast<size_t>(task.split_first) * a.Kp;
+#pragma unroll
+                for (int m = 0; m < QPL; ++m) {
+                    const int q = quad_of<LPG>(lane, m);
+                    acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (q >= a.nq) continue;
+                    for (int s = 0; s < task.n_split; ++s) {
+                        const float *pq = first + static_cast<size_t>(s) * a.Kp + 4 * q;
+                        acc[m].x += __hip_atomic_load(pq + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        acc[m].y += __hip_atomic_load(pq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        acc[m].z += __hip_atomic_load(pq + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        acc[m].w += __hip_atomic_load(pq + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
                 }
             }
         } else {
@@ -330,20 +388,20 @@ __device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterS
         }
     }
 
-    if (lead) item_update<LPG>(a, it, task.side, rec.item, st.x, acc, lane, qlane);
+    if (lead) item_update<LPG, QPL>(a, it, task.side, rec.item, st.x, acc, lane);
 }
 
 // One work-group per task of the part.
-template <int LPG, int LIK>
+template <int LPG, int QPL, int LIK>
 __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterArgs a)
 {
-    sparse_task<LPG, LIK>(a, iter_scalars(a.clk), blockIdx.x);
+    sparse_task<LPG, QPL, LIK>(a, iter_scalars(a.clk), blockIdx.x);
 }
 
 // Several contexts in one launch: the work-group finds its context, reads
 // the context's clock, and runs task (blockIdx - first) of the current part
 // with exactly the arguments a single-context launch would pass.
-template <int LPG, int LIK>
+template <int LPG, int QPL, int LIK>
 __global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b)
 {
     const int wg = blockIdx.x;
@@ -398,7 +456,7 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b
     a.ho_sum = d.ho_sum;
     a.nonfinite = d.nonfinite;
     const IterScalars it = iter_scalars_at(t, d.eps_tab, d.burn_in, d.thin, true, d.has_heldout != 0);
-    sparse_task<LPG, LIK>(a, it, task);
+    sparse_task<LPG, QPL, LIK>(a, it, task);
 }
 
 struct ClockList {
@@ -411,30 +469,30 @@ __global__ void advance_clocks_kernel(ClockList l)
     if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += 1;
 }
 
-template <int LPG>
+template <int LPG, int QPL>
 hipError_t launch_batch_lpg(const BatchArgs &b, int lik, hipStream_t stream)
 {
     const dim3 grid(static_cast<unsigned>(b.wg_first[b.n])), block(kBlockThreads);
     switch (lik) {
-    case LIK_GAUSS: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GAUSS>), grid, block, 0, stream, b); break;
-    case LIK_POISSON: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_POISSON>), grid, block, 0, stream, b); break;
-    case LIK_HALF: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_HALF>), grid, block, 0, stream, b); break;
-    case LIK_GAMMA: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GAMMA>), grid, block, 0, stream, b); break;
-    default: hipLaunchKernelGGL((sparse_batch_kernel<LPG, LIK_GENERAL>), grid, block, 0, stream, b); break;
+    case LIK_GAUSS: hipLaunchKernelGGL((sparse_batch_kernel<LPG, QPL, LIK_GAUSS>), grid, block, 0, stream, b); break;
+    case LIK_POISSON: hipLaunchKernelGGL((sparse_batch_kernel<LPG, QPL, LIK_POISSON>), grid, block, 0, stream, b); break;
+    case LIK_HALF: hipLaunchKernelGGL((sparse_batch_kernel<LPG, QPL, LIK_HALF>), grid, block, 0, stream, b); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((sparse_batch_kernel<LPG, QPL, LIK_GAMMA>), grid, block, 0, stream, b); break;
+    default: hipLaunchKernelGGL((sparse_batch_kernel<LPG, QPL, LIK_GENERAL>), grid, block, 0, stream, b); break;
     }
     return hipGetLastError();
 }
 
-template <int LPG>
+template <int LPG, int QPL>
 hipError_t launch_lpg(const SparseIterArgs &a, int lik, hipStream_t stream)
 {
     const dim3 grid(static_cast<unsigned>(a.n_tasks)), block(kBlockThreads);
     switch (lik) {
-    case LIK_GAUSS: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GAUSS>), grid, block, 0, stream, a); break;
-    case LIK_POISSON: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_POISSON>), grid, block, 0, stream, a); break;
-    case LIK_HALF: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_HALF>), grid, block, 0, stream, a); break;
-    case LIK_GAMMA: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GAMMA>), grid, block, 0, stream, a); break;
-    default: hipLaunchKernelGGL((sparse_iter_kernel<LPG, LIK_GENERAL>), grid, block, 0, stream, a); break;
+    case LIK_GAUSS: hipLaunchKernelGGL((sparse_iter_kernel<LPG, QPL, LIK_GAUSS>), grid, block, 0, stream, a); break;
+    case LIK_POISSON: hipLaunchKernelGGL((sparse_iter_kernel<LPG, QPL, LIK_POISSON>), grid, block, 0, stream, a); break;
+    case LIK_HALF: hipLaunchKernelGGL((sparse_iter_kernel<LPG, QPL, LIK_HALF>), grid, block, 0, stream, a); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((sparse_iter_kernel<LPG, QPL, LIK_GAMMA>), grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL((sparse_iter_kernel<LPG, QPL, LIK_GENERAL>), grid, block, 0, stream, a); break;
     }
     return hipGetLastError();
 }
@@ -443,28 +501,44 @@ hipError_t launch_lpg(const SparseIterArgs &a, int lik, hipStream_t stream)
 
 int sparse_block_threads() { return kBlockThreads; }
 
-// Lanes per item group: the smallest power of two covering ceil(K/4) quads.
+// Quads (float4 of k) per lane: 1 up to K = 16, else 2, which halves the
+// lanes (and waves) per item for the mid-size ranks.
+int sparse_quads_per_lane(int K)
+{
+    return (K + 3) / 4 <= 4 ? 1 : 2;
+}
+
+// Lanes per item group: the smallest power of two covering the quads.
 int sparse_threads_per_group(int K)
 {
-    const int nq = (K + 3) / 4;
+    const int qpl = sparse_quads_per_lane(K);
+    const int need = ((K + 3) / 4 + qpl - 1) / qpl;
     int lpg = 1;
-    while (lpg < nq) lpg *= 2;
+    while (lpg < need) lpg *= 2;
     return lpg;
 }
 
-hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, hipStream_t stream)
+hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, int qpl, hipStream_t stream)
 {
     if (b.n <= 0 || b.n > kMaxBatch || b.wg_first[b.n] == 0) return b.n > kMaxBatch ? hipErrorInvalidValue : hipSuccess;
-    switch (lpg) {
-    case 1: return launch_batch_lpg<1>(b, lik, stream);
-    case 2: return launch_batch_lpg<2>(b, lik, stream);
-    case 4: return launch_batch_lpg<4>(b, lik, stream);
-    case 8: return launch_batch_lpg<8>(b, lik, stream);
-    case 16: return launch_batch_lpg<16>(b, lik, stream);
-    case 32: return launch_batch_lpg<32>(b, lik, stream);
-    case 64: return launch_batch_lpg<64>(b, lik, stream);
-    default: return hipErrorInvalidValue;
+    if (qpl == 1) {
+        switch (lpg) {
+        case 1: return launch_batch_lpg<1, 1>(b, lik, stream);
+        case 2: return launch_batch_lpg<2, 1>(b, lik, stream);
+        case 4: return launch_batch_lpg<4, 1>(b, lik, stream);
+        default: return hipErrorInvalidValue;
+        }
     }
+    if (qpl == 2) {
+        switch (lpg) {
+        case 4: return launch_batch_lpg<4, 2>(b, lik, stream);
+        case 8: return launch_batch_lpg<8, 2>(b, lik, stream);
+        case 16: return launch_batch_lpg<16, 2>(b, lik, stream);
+        case 32: return launch_batch_lpg<32, 2>(b, lik, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream)
@@ -480,19 +554,27 @@ hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stre
     return hipSuccess;
 }
 
-hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lpg, hipStream_t stream)
+hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lpg, int qpl, hipStream_t stream)
 {
     if (a.n_tasks == 0) return hipSuccess;
-    switch (lpg) {
-    case 1: return launch_lpg<1>(a, lik, stream);
-    case 2: return launch_lpg<2>(a, lik, stream);
-    case 4: return launch_lpg<4>(a, lik, stream);
-    case 8: return launch_lpg<8>(a, lik, stream);
-    case 16: return launch_lpg<16>(a, lik, stream);
-    case 32: return launch_lpg<32>(a, lik, stream);
-    case 64: return launch_lpg<64>(a, lik, stream);
-    default: return hipErrorInvalidValue;
+    if (qpl == 1) {
+        switch (lpg) {
+        case 1: return launch_lpg<1, 1>(a, lik, stream);
+        case 2: return launch_lpg<2, 1>(a, lik, stream);
+        case 4: return launch_lpg<4, 1>(a, lik, stream);
+        default: return hipErrorInvalidValue;
+        }
     }
+    if (qpl == 2) {
+        switch (lpg) {
+        case 4: return launch_lpg<4, 2>(a, lik, stream);
+        case 8: return launch_lpg<8, 2>(a, lik, stream);
+        case 16: return launch_lpg<16, 2>(a, lik, stream);
+        case 32: return launch_lpg<32, 2>(a, lik, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace psgld

@@ -5,7 +5,9 @@ is stepped on the GPU with the schedule bench.py tunes, and single steps
 (t = 0 and mid-run) are compared element by element with the FP64 oracle's
 full step.  The dense spectrogram-shaped workload keeps its block shape
 (1025 rows in 16 pieces of 64-65 rows, K = 64, beta = 0.5) on 4,000 columns so
-the oracle finishes in seconds."""
+the oracle finishes in seconds.  The large ratings workload (480,000 x
+17,800, 100M entries, K = 100, B = 64) runs with a tenth of its rows and
+entries."""
 import numpy as np
 import pytest
 
@@ -36,3 +38,17 @@ def test_dense_tweedie_block_shape_parity(bf16):
     s.close()
     tol = TOL_BF16 if bf16 else TOL_FP32
     assert err0 <= tol and err1 <= tol, (err0, err1)
+
+
+def test_large_ratings_shape_step_parity():
+    """The 480,000 x 17,800 workload's kernel variant and skew (K = 100,
+    B = 64, Zipf 1.1 columns, lognormal rows) on a tenth of its rows and
+    entries, with the schedule the benchmark tunes."""
+    wl = workloads.sparse_ratings(I=48_000, J=17_800, nnz=10_000_000, K_true=30, K=100, B=64, zipf_a=1.1,
+                                  data_seed=1004, chain_seed=2004, name="sparse_ratings_48k")
+    s = pkg.PSGLD.from_workload(wl)
+    s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(16, 32, 64, 128), iters=wl.B)
+    err0, _ = step_parity(wl, 0, sampler=s)
+    err1, _ = step_parity(wl, 9, sampler=s)
+    s.close()
+    assert err0 <= TOL_FP32 and err1 <= TOL_FP32, (err0, err1)
