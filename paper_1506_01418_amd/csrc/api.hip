@@ -939,7 +939,7 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
             blk.n_tiles = (blk.n + wg_cols - 1) / wg_cols;
             const int32_t idx_in_part = static_cast<int32_t>(c->dblocks_host.size() - c->dblk_off[p]);
             for (int32_t tt = 0; tt < blk.n_tiles; ++tt)
-                tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, 0, 0, {0, 0, 0}});
+                tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, {0, 0, 0, 0, 0}});
             partial += blk.n_tiles;
             for (int64_t i = 0; i < blk.m; ++i)
                 for (int64_t j = 0; j < blk.n; ++j) {
@@ -1039,9 +1039,13 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
         std::sort(dh[w].begin(), dh[w].end(), [](const DenseHeld &a, const DenseHeld &b) {
             return a.col != b.col ? a.col < b.col : a.row < b.row;
         });
-        c->dtiles_host[w].ho_begin = static_cast<int32_t>(dflat.size());
+        const int32_t first = static_cast<int32_t>(dflat.size());
+        for (int sub = 0; sub <= kDenseSubTiles; ++sub)
+            c->dtiles_host[w].ho[sub] =
+                first + static_cast<int32_t>(std::lower_bound(dh[w].begin(), dh[w].end(), sub * kDenseTileCols,
+                                                              [](const DenseHeld &h, int32_t col) { return h.col < col; }) -
+                                             dh[w].begin());
         dflat.insert(dflat.end(), dh[w].begin(), dh[w].end());
-        c->dtiles_host[w].ho_end = static_cast<int32_t>(dflat.size());
     }
     if (!c->dblocks_host.empty()) {
         HIPTRY(c, hipMemcpy(c->dtiles, c->dtiles_host.data(), c->dtiles_host.size() * sizeof(DenseTile),

@@ -100,13 +100,22 @@ __device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, const Ite
     *reinterpret_cast<float4 *>(a.x_new[side] + off) = make_float4(xn[0], xn[1], xn[2], xn[3]);
     if (!finite) atomicMin(a.nonfinite, static_cast<int32_t>(it.t));
     if (it.do_moments) {
-        double *s = a.sum[side] + off;
-        double *s2 = a.sum2[side] + off;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            s[c] += static_cast<double>(xn[c]);
-            s2[c] += static_cast<double>(xn[c]) * static_cast<double>(xn[c]);
-        }
+        double2 *s = reinterpret_cast<double2 *>(a.sum[side] + off);
+        double2 *s2 = reinterpret_cast<double2 *>(a.sum2[side] + off);
+        const double d0 = xn[0], d1 = xn[1], d2 = xn[2], d3 = xn[3];
+        double2 p0 = s[0], p1 = s[1], q0 = s2[0], q1 = s2[1];
+        p0.x += d0;
+        p0.y += d1;
+        p1.x += d2;
+        p1.y += d3;
+        q0.x += d0 * d0;
+        q0.y += d1 * d1;
+        q1.x += d2 * d2;
+        q1.y += d3 * d3;
+        s[0] = p0;
+        s[1] = p1;
+        s2[0] = q0;
+        s2[1] = q1;
     }
 }
 
@@ -115,11 +124,62 @@ __device__ __forceinline__ void dense_langevin(const DenseIterArgs &a, const Ite
 // products over the rank (G_H and G_W) use one 16-row k-tile per wave
 // (K <= 64).  G_W accumulates in registers over the sub-tiles and is
 // written once, as this work-group's partial.
+__device__ __forceinline__ float4 load4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+
+// Register staging of a 64-column piece of a factor stored row by row with
+// Kp floats per row: 16 quad slots per row (K <= 64), kStageQ float4 per
+// thread, consecutive threads on consecutive quads of a row, so a wave reads
+// four whole rows.  Slots past the rows asked for, or past Kp, hold zeros.
+constexpr int kStageQ = kNT * (kDenseMaxK / 4) / kDenseThreads;
+
+struct Stage {
+    float4 v[kStageQ];
+};
+
+__device__ __forceinline__ void stage_load(Stage &st, const float *base, int first_row, int nrows, int Kp, int tid)
+{
+#pragma unroll
+    for (int u = 0; u < kStageQ; ++u) {
+        const int f = tid + u * kDenseThreads;
+        const int j = f >> 4, q = f & 15;
+        st.v[u] = (j < nrows && 4 * q < Kp) ? load4(base + static_cast<size_t>(first_row + j) * Kp + 4 * q)
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Writes the staged rows j (of 64) into LDS rows j0 + j < rows with stride
+// `stride`, columns 0 .. KS - 1.
+__device__ __forceinline__ void stage_store(const Stage &st, float *lds, int j0, int rows, int stride, int KS,
+                                            int tid)
+{
+#pragma unroll
+    for (int u = 0; u < kStageQ; ++u) {
+        const int f = tid + u * kDenseThreads;
+        const int j = f >> 4, q = f & 15;
+        if (4 * q < KS && j0 + j < rows) {
+            float *d = lds + (j0 + j) * stride + 4 * q;
+            d[0] = st.v[u].x;
+            d[1] = st.v[u].y;
+            d[2] = st.v[u].z;
+            d[3] = st.v[u].w;
+        }
+    }
+}
+
+// One work-group: up to kDenseSubTiles consecutive 64-column sub-tiles of
+// one block.  Wave w takes 16-row tiles w, w+4, ... of mu; the products over
+// the rank (G_H and G_W) use one 16-row k-tile per wave (K <= 64).  The next
+// sub-tile's H columns are loaded into registers while the current one is
+// computed, and each row tile's values and mask bytes are loaded before its
+// product, so no product waits on a round trip to memory it could have
+// started earlier.  G_W accumulates in registers over the sub-tiles and is
+// written once, as this work-group's partial.
 template <bool BF16, int LIK>
 __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs a)
 {
     extern __shared__ float lds[];
     const DenseTile tile = a.tiles[blockIdx.x];
+    const int32_t *ho = a.tiles[blockIdx.x].ho;   // read in place: indexed by the sub-tile
     const DenseBlock blk = a.blocks[tile.block];
     const IterScalars itr = iter_scalars(a.clk);
     const int m = blk.m, MT = (m + a.row_align - 1) / a.row_align * a.row_align;
@@ -133,9 +193,13 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
     const int c16 = lane & 15, h4 = lane >> 4;
     const float *Wold = a.x_old[0], *Hold = a.x_old[1];
 
-    for (int i = wave; i < MT; i += kDenseThreads / 64)
-        for (int k = lane; k < KS; k += 64)
-            sW[i * sw + k] = (i < m && k < Kp) ? Wold[static_cast<size_t>(blk.row0 + i) * Kp + k] : 0.f;
+    // W_b (two 64-row pieces) and the first sub-tile's H columns, all in flight together
+    Stage hs, ws0, ws1;
+    stage_load(hs, Hold, blk.col0 + tile.col, min(kNT, blk.n - tile.col), Kp, tid);
+    stage_load(ws0, Wold, blk.row0, min(kNT, m), Kp, tid);
+    if (MT > kNT) stage_load(ws1, Wold, blk.row0 + kNT, m - kNT, Kp, tid);
+    stage_store(ws0, sW, 0, MT, sw, KS, tid);
+    if (MT > kNT) stage_store(ws1, sW, kNT, MT, sw, KS, tid);
 
     const float *V = a.val + blk.v_off;
     const uint8_t *M = a.mask + blk.v_off;
@@ -152,13 +216,27 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
         const int ncol = min(kNT, blk.n - cl);
         const int col0 = blk.col0 + cl;
         __syncthreads();                          // previous sub-tile done with sH, sE
-        for (int j = wave; j < kNT; j += kDenseThreads / 64)
-            for (int k = lane; k < KS; k += 64)
-                sH[j * sw + k] = (j < ncol && k < Kp) ? Hold[static_cast<size_t>(col0 + j) * Kp + k] : 0.f;
+        stage_store(hs, sH, 0, kNT, sw, KS, tid);
+        if (sub + 1 < kDenseSubTiles && cl + kNT < blk.n)
+            stage_load(hs, Hold, col0 + kNT, min(kNT, blk.n - cl - kNT), Kp, tid);
         __syncthreads();
 
-        // mu = W_b H^T (MT x 64) and E
+        // mu = W_b H^T (MT x 64) and E, one 16-row tile at a time; the tile's
+        // values and mask bytes (clamped into the block, masked after) are
+        // requested before its product
         for (int it = wave; it < n_it; it += kDenseThreads / 64) {
+            float vv[4][4];
+            uint32_t mm[4][4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = min(it * 16 + 4 * h4 + r, m - 1);
+                    const int j = min(t * 16 + c16, ncol - 1);
+                    const size_t cell = static_cast<size_t>(i) * blk.n + cl + j;
+                    vv[t][r] = V[cell];
+                    mm[t][r] = M[cell];
+                }
             v4f acc[4] = {};
             mma16<BF16, 4>(acc, 4, KS, lane, [&](int r, int k) { return sW[(it * 16 + r) * sw + k]; },
                            [&](int t, int k, int c) { return sH[(t * 16 + c) * sw + k]; });
@@ -170,26 +248,22 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
                     const int i = it * 16 + 4 * h4 + r;
                     // E for training cells; the mean itself for held-out cells
                     // (read out and cleared below, before the products use E)
+                    const bool inside = i < m && j < ncol;
+                    const float res = tweedie_residual<LIK>(vv[t][r], acc[t][r], a.inv_phi, a.beta, a.mu_floor);
                     float e = 0.f;
-                    if (i < m && j < ncol) {
-                        const size_t cell = static_cast<size_t>(i) * blk.n + cl + j;
-                        const uint8_t mk = M[cell];
-                        if (mk == kMaskTrain)
-                            e = tweedie_residual<LIK>(V[cell], acc[t][r], a.inv_phi, a.beta, a.mu_floor);
-                        else if (mk == kMaskHeld && itr.do_heldout)
-                            e = acc[t][r];
-                    }
+                    if (inside && mm[t][r] == kMaskTrain) e = res;
+                    if (inside && mm[t][r] == kMaskHeld && itr.do_heldout) e = acc[t][r];
                     sE[i * se + j] = e;
                 }
             }
         }
         __syncthreads();
-        if (itr.do_heldout && tile.ho_end > tile.ho_begin) {
+        const int ho_b = ho[sub], ho_e = ho[sub + 1];
+        if (itr.do_heldout && ho_e > ho_b) {
             // held-out cells of this sub-tile: add their mean, then zero them in E
-            for (int h = tile.ho_begin + tid; h < tile.ho_end; h += kDenseThreads) {
+            for (int h = ho_b + tid; h < ho_e; h += kDenseThreads) {
                 const DenseHeld c = a.heldout[h];
                 const int j = c.col - sub * kNT;
-                if (j < 0 || j >= kNT) continue;
                 a.ho_sum[c.slot] += static_cast<double>(sE[c.row * se + j]);
                 sE[c.row * se + j] = 0.f;
             }

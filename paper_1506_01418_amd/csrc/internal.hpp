@@ -213,14 +213,13 @@ struct DenseBlock {
 };
 
 // One work-group's share of a block: columns [col, col + kDenseSubTiles * 64)
-// of part block `block`; its W partial goes to slot `partial`; its held-out
-// cells are heldout[ho_begin .. ho_end) (in column order).
+// of part block `block`; its W partial goes to slot `partial`; the held-out
+// cells of its sub-tile s are heldout[ho[s] .. ho[s + 1]).
 struct DenseTile {
     int32_t block;
     int32_t col;
     int32_t partial;
-    int32_t ho_begin, ho_end;
-    int32_t pad[3];
+    int32_t ho[kDenseSubTiles + 1];
 };
 
 // Dense-block mask byte: 0 missing, 1 training cell, 2 held-out cell.
