@@ -68,13 +68,12 @@ class HipEvents:
         assert self.hip.hipDeviceSynchronize() == 0
 
 
-def algorithmic_bytes(wl, n_p, ho_p, t):
+def algorithmic_bytes(wl, n_p, ho_p, t, p):
     """Bytes one iteration must move at minimum: each training entry of the
     part read once (4-byte index + 4-byte value), every factor element read
     and written once in FP32, the FP64 sums of x and x^2 read and written at
     kept iterations, one FP64 read-modify-write per held-out cell of the part
-    after burn-in."""
-    p = t % wl.B
+    after burn-in.  p is the part of iteration t."""
     b = 8 * n_p[p] + 8 * (wl.I + wl.J) * wl.K
     if t >= wl.burn_in:
         b += 16 * ho_p[p]
@@ -91,18 +90,52 @@ def dense_part_cells(wl):
     return np.array([sum(int(rp[b]) * int(cp[(b + p) % wl.B]) for b in range(wl.B)) for p in range(wl.B)])
 
 
-def dense_algorithmic(wl, cells_p, ho_p, t):
+def dense_algorithmic(wl, cells_p, ho_p, t, p):
     """(bytes, flops) of one dense iteration: every cell of the part's blocks
     read once (FP32 value + mask byte), factors read and written once in
     FP32, FP64 sums at kept iterations, FP64 held-out sums after burn-in; 6K
-    flops per cell for mu = W H, G_H = W^T E and G_W = E H^T."""
-    p = t % wl.B
+    flops per cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the part
+    of iteration t."""
     b = 5 * cells_p[p] + 8 * (wl.I + wl.J) * wl.K
     if t >= wl.burn_in:
         b += 16 * ho_p[p]
         if (t - wl.burn_in) % wl.thin == 0:
             b += 32 * (wl.I + wl.J) * wl.K
     return b, 6 * wl.K * cells_p[p]
+
+
+# Sources of each kernel family: a traffic measurement stored in
+# profiles/traffic.json applies only while these files are unchanged.
+KERNEL_SOURCES = {
+    "sparse": ["sparse.hip", "internal.hpp", "noise.hpp", "model.hpp"],
+    "dense": ["dense.hip", "internal.hpp", "noise.hpp", "model.hpp"],
+}
+
+
+def source_digest(kind):
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1506_01418_amd", "csrc")
+    for name in KERNEL_SOURCES[kind]:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key, kind):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters stored in
+    profiles/traffic.json (each scaled by the copy-kernel reference), or None
+    when there is no measurement or the kernel's sources changed since."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    run = data.get("runs", {}).get(key)
+    if not run or run.get("source_sha256") != source_digest(kind):
+        return None
+    ref = data["copy_reference"]
+    return 1024.0 * (run["FETCH_SIZE_KiB"] * ref["fetch_scale"] + run["WRITE_SIZE_KiB"] * ref["write_scale"])
 
 
 def make_workload(name):
@@ -128,15 +161,18 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wl, iters):
+def cpu_baseline(wl, iters, part_order="cyclic", row_piece=None, col_piece=None):
     import oracle
     cfg = oracle.Config(**wl.fit_kwargs())
-    ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+    cfg.part_order = part_order
+    ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol,
+                      row_piece=row_piece, col_piece=col_piece)
     n_p = ch.part_sizes()
+    parts = [ch.part_at(t) for t in range(iters)]
     t0 = time.perf_counter()
     ch.run(iters)
     dt = time.perf_counter() - t0
-    entries = int(sum(n_p[t % wl.B] for t in range(iters)))
+    entries = int(sum(n_p[p] for p in parts))
     return {"value": entries / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} iterations from t=0 ({iters / wl.B:g} cycles of the {wl.B} parts) "
                       f"of the same workload, single-threaded FP64 C, {dt:.1f} s incl. its setup"}
@@ -156,7 +192,7 @@ def serve_main(args):
           f"({sum(wl.nnz for wl in jobs)} training entries, {sum(wl.dense is not None for wl in jobs)} dense)",
           file=sys.stderr, flush=True)
     srv = pkg.Server(int(args.budget_gib * (1 << 30)), max_active=args.max_active,
-                     iters_per_tick=args.iters_per_tick)
+                     iters_per_tick=args.iters_per_tick, persistent=args.persistent)
     # warm-up: one small job through the whole path (kernel loading, allocator)
     wid = srv.submit(workloads.serving_job(10_000, T=args.iters_per_tick, burn_in=0), args.iters_per_tick)
     while srv.tick()[:2] != (0, 0):
@@ -201,6 +237,7 @@ def serve_main(args):
         "config": {"workload": f"serve_c5_{args.jobs}jobs", "jobs": args.jobs, "rate_per_s": args.rate,
                    "hbm_budget_gib": args.budget_gib, "iters_per_job": args.job_iters,
                    "iters_per_tick": args.iters_per_tick, "max_active": args.max_active,
+                   "persistent": bool(args.persistent),
                    "parallelism": "single-gpu"},
         "serving": {"p50_ms": p50 * 1e3, "p99_ms": p99 * 1e3, "jobs_per_s": args.jobs / makespan,
                     "makespan_s": makespan, "ticks": ticks, "max_running": max_running},
@@ -231,6 +268,15 @@ def main():
     ap.add_argument("--iters-per-tick", type=int, default=25, help="serve_c5: iterations per job per tick")
     ap.add_argument("--max-active", type=int, default=64, help="serve_c5: running jobs at most")
     ap.add_argument("--job-iters", type=int, default=500, help="serve_c5: iterations per job")
+    ap.add_argument("--persistent", action="store_true",
+                    help="run iterations in cooperative single launches (coordinate-stored contexts)")
+    ap.add_argument("--graph-iters", type=int, default=-1,
+                    help="iterations per captured graph (<0: no capture, the default; 0: whole cycles)")
+    ap.add_argument("--coo", action="store_true", help="load a dense workload as coordinates")
+    ap.add_argument("--balanced", action="store_true",
+                    help="row and column pieces balancing training entries (psgld_balanced_pieces)")
+    ap.add_argument("--part-order", choices=["cyclic", "random"], default="cyclic",
+                    help="cyclic parts, or parts drawn with probability |part| / N")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -249,10 +295,15 @@ def main():
           f"({time.perf_counter() - t_gen:.1f} s to generate)", file=sys.stderr, flush=True)
 
     ev = HipEvents()
-    dense = wl.dense is not None
+    dense = wl.dense is not None and not args.coo
     prec = pkg.PSGLD_BF16_DENSE if args.precision == "bf16" else pkg.PSGLD_FP32
     t_load = time.perf_counter()
-    s = pkg.PSGLD.from_workload(wl, dense=dense, precision=prec)
+    pieces = {}
+    if args.balanced and not dense:
+        rp, cp = pkg.balanced_pieces_for(wl.row, wl.col, wl.I, wl.J, wl.B)
+        pieces = {"row_piece": rp, "col_piece": cp}
+    s = pkg.PSGLD.from_workload(wl, dense=dense, precision=prec, graph_iters=args.graph_iters,
+                                persistent=args.persistent, part_order=args.part_order, **pieces)
     print(f"[bench] loaded in {time.perf_counter() - t_load:.1f} s", file=sys.stderr, flush=True)
     stream = s.stream()
     chosen = None
@@ -263,7 +314,9 @@ def main():
         print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
               file=sys.stderr, flush=True)
     n_p, N = s.part_sizes()
-    ho_part = (np.asarray(pkg_pieces(wl, "col"))[wl.hcol] - np.asarray(pkg_pieces(wl, "row"))[wl.hrow]) % wl.B
+    rpc = pieces.get("row_piece", pkg_pieces(wl, "row"))
+    cpc = pieces.get("col_piece", pkg_pieces(wl, "col"))
+    ho_part = (np.asarray(cpc)[wl.hcol] - np.asarray(rpc)[wl.hrow]) % wl.B
     ho_p = np.bincount(ho_part, minlength=wl.B)
     state0 = s.get_state()
 
@@ -281,7 +334,8 @@ def main():
     elapsed_ms = ev.elapsed_ms(e0, e1)
     s.sync()
     ev.sync()
-    entries = int(sum(n_p[t % wl.B] for t in range(args.steps)))
+    parts = [s.part_at(t) for t in range(args.steps)]
+    entries = int(sum(n_p[p] for p in parts))
     value = entries / (elapsed_ms * 1e-3)
     rmse = s.heldout_rmse() if args.steps > wl.burn_in else None
     print(f"[bench] pass 1: {args.steps} iterations in {elapsed_ms:.3f} ms, "
@@ -301,7 +355,8 @@ def main():
     avg_ms = float(durs.mean())
     if dense:
         cells_p = dense_part_cells(wl)
-        bf = np.array([dense_algorithmic(wl, cells_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
+        bf = np.array([dense_algorithmic(wl, cells_p, ho_p, t, parts[t]) for t in range(args.steps)],
+                      dtype=np.float64)
         alg, flops = bf[:, 0], bf[:, 1]
         t_hbm = alg.mean() / (HBM_PEAK_GBS * 1e9)
         t_mfma = flops.mean() / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
@@ -313,14 +368,17 @@ def main():
             achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS}
-        roof.update({"traffic": None, "kernel": "dense iteration (dense_tile_kernel + dense_w_update_kernel"
-                     " + dense_heldout_kernel)", "avg_launch_us": avg_ms * 1e3,
+        roof.update({"traffic": measured_traffic(f"{wl.name}:{args.precision}", "dense"),
+                     "kernel": "dense iteration (dense_tile_kernel + dense_w_update_kernel)",
+                     "avg_launch_us": avg_ms * 1e3,
                      "alg_bytes_per_launch": float(alg.mean()), "flops_per_launch": float(flops.mean())})
     else:
-        alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t) for t in range(args.steps)], dtype=np.float64)
+        alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t, parts[t]) for t in range(args.steps)],
+                       dtype=np.float64)
         achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sparse_iter_kernel",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl.name, "sparse"),
+                "kernel": "sparse_iter_kernel",
                 "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": float(alg.mean())}
     print(f"[bench] pass 2: iteration avg {avg_ms * 1e3:.2f} us, roofline {roof['achieved']:.1f} "
           f"{roof['unit']} ({roof['bound']}), RMSE {rmse2}", file=sys.stderr, flush=True)
@@ -328,7 +386,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_iters)
+        cpu = cpu_baseline(wl, args.cpu_iters, args.part_order, pieces.get("row_piece"), pieces.get("col_piece"))
         print(f"[bench] oracle: {cpu['value']:.4g} updates/s", file=sys.stderr, flush=True)
 
     out = {
@@ -341,7 +399,10 @@ def main():
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
                    "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
                    "heldout_rmse": rmse, "entries_per_group": chosen, "dense": dense,
-                   "precision": args.precision if dense else "f32", "parallelism": "single-gpu"},
+                   "precision": args.precision if dense else "f32", "parallelism": "single-gpu",
+                   "part_order": args.part_order, "balanced_pieces": bool(pieces),
+                   "launch": "persistent" if args.persistent and not dense else
+                             ("graph" if args.graph_iters >= 0 else "per-iteration")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -85,6 +85,12 @@ typedef struct {
 } psgld_eps_schedule;
 
 enum { PSGLD_FP32 = 0, PSGLD_BF16_DENSE = 1 };
+/* Part order: cyclic, p_t = t mod B (Section 4.2.1), or drawn at every
+ * iteration with probability |part| / N (Condition 2) from the Philox stream
+ * PART = 4: counter (0, 0, t, 4), u = (2 (r0 >> 9) + 1) 2^-24, part = the
+ * first p with u N < n_0 + ... + n_p (compared exactly on integers scaled by
+ * 2^24); cyclic when there are no entries. */
+enum { PSGLD_PART_CYCLIC = 0, PSGLD_PART_RANDOM = 1 };
 enum {
     PSGLD_TEST_NOISE_OFF = 1u,  /* z = 0: the chain becomes parallel SGD */
     PSGLD_TEST_FREEZE_W = 2u,   /* W is not updated */
@@ -104,14 +110,22 @@ typedef struct {
     uint32_t test_flags;      /* PSGLD_TEST_* (test use only) */
     int32_t device;           /* HIP device ordinal */
     int32_t graph_iters;      /* iterations per captured HIP graph in psgld_step:
-                                 0 = one cycle of B parts repeated to at least 32
-                                 iterations; < 0 = never capture (one launch
-                                 sequence per iteration) */
+                                 < 0 = never capture, one launch sequence per
+                                 iteration (the default: on MI355X it measured
+                                 faster than graph replay); 0 = one cycle of B
+                                 parts repeated to at least 32 iterations;
+                                 > 0 = that many iterations */
+    int32_t persistent;       /* 1: contexts without dense blocks run their
+                                 iterations in cooperative single launches of up
+                                 to 256 iterations (grid-wide barrier between
+                                 iterations; no graph); 0 = off */
+    int32_t part_order;       /* PSGLD_PART_CYCLIC (default) or PSGLD_PART_RANDOM;
+                                 random order is never captured into graphs */
 } psgld_options;
 
 /* Fills *opt with the defaults: seed 0, burn_in 0, thin 1, FP32,
  * dense_threshold 0.3, mu_floor 1e-6, contiguous pieces, own stream,
- * no test flags, device 0, graph_iters 0. */
+ * no test flags, device 0, graph_iters -1, persistent 0, cyclic part order. */
 void psgld_default_options(psgld_options *opt);
 
 /* Creates a context for an I x J matrix, rank K (1..256), B x B blocks
@@ -171,7 +185,10 @@ psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule
  * inside the same loop.  Each context's results are bitwise those of
  * psgld_step on it alone: the contexts share no memory.  All contexts must be
  * distinct and share one device and one stream (options.stream), else E_ARG;
- * each needs data and factors (E_STATE).  Asynchronous like psgld_step. */
+ * each needs data and factors (E_STATE).  When every coordinate-stored
+ * context has options.persistent set, each group of contexts with the same
+ * variant and iteration count runs all its iterations in one cooperative
+ * launch instead.  Asynchronous like psgld_step. */
 psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *n_iter,
                               const psgld_eps_schedule *scheds);
 
@@ -263,6 +280,20 @@ psgld_status psgld_normals(int64_t n, uint64_t seed, const int64_t *t, const uin
                            const int64_t *index, int32_t K, float *z, float *radius,
                            int32_t device);
 
+/* The part (0 .. B-1) iteration t uses under the context's part order.
+ * Needs loaded data (E_STATE). */
+psgld_status psgld_part_at(psgld_ctx *ctx, int64_t t, int32_t *part);
+
+/* Data-dependent pieces (Section 3 lets the pieces be any partition): each
+ * of the n elements (rows or columns) with weight[m] >= 0 (e.g. its number
+ * of training entries plus one for its own update) is put into one of B
+ * pieces, heaviest first, each into the piece with the least weight so far
+ * (lowest index on ties), so no piece is empty when n >= B and the heaviest
+ * piece exceeds the lightest by at most the largest single weight.
+ * Deterministic.  piece[n] is written.  Host only; E_ARG if n < B, B < 1 or
+ * a weight is negative.  Use the result as options.row_piece / col_piece. */
+psgld_status psgld_balanced_pieces(int64_t n, const int64_t *weight, int32_t B, int32_t *piece);
+
 /* ---------------------------------------------------------------------
  * Serving: many independent PSGLD runs ("jobs") on one device.
  *
@@ -285,6 +316,7 @@ typedef struct {
     int32_t max_active;       /* running jobs at most; >= 1 */
     int32_t iters_per_tick;   /* iterations per job per tick; >= 1 */
     int32_t device;           /* HIP device ordinal */
+    int32_t persistent;       /* 1: a tick runs in cooperative launches (options.persistent of the jobs) */
 } psgld_server_options;
 
 /* One complete run.  Data as for psgld_load_coo (row != NULL) or

@@ -39,6 +39,9 @@ def build() -> str:
     return _LIB
 
 
+PART_ORDERS = {"cyclic": 0, "random": 1}
+
+
 class _Cfg(C.Structure):
     _fields_ = [("I", C.c_int64), ("J", C.c_int64), ("K", C.c_int32), ("B", C.c_int32),
                 ("beta", C.c_double), ("phi", C.c_double), ("mu_floor", C.c_double),
@@ -46,7 +49,7 @@ class _Cfg(C.Structure):
                 ("lambda_w", C.c_double), ("lambda_h", C.c_double),
                 ("eps_a", C.c_double), ("eps_t0", C.c_double), ("eps_gamma", C.c_double),
                 ("seed", C.c_uint64), ("burn_in", C.c_int64), ("thin", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("part_order", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -85,6 +88,8 @@ def lib():
         L.oracle_loglik.restype = C.c_int
         L.oracle_run.argtypes = [C.POINTER(_Cfg), C.POINTER(_State), C.c_int64, _P, _P]
         L.oracle_run.restype = C.c_int
+        L.oracle_part_at.argtypes = [C.POINTER(_Cfg), C.c_int64, _P, C.c_int64]
+        L.oracle_part_at.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -144,12 +149,13 @@ class Config:
     thin: int = 1
     flags: int = 0
     mu_floor: float = 1e-6
+    part_order: str = "cyclic"    # or "random": parts drawn with probability |part| / N
 
     def c(self) -> _Cfg:
         return _Cfg(self.I, self.J, self.K, self.B, self.beta, self.phi, self.mu_floor,
                     PRIOR_KINDS[self.prior], int(bool(self.mirror)), self.lambda_w, self.lambda_h,
                     self.eps_a, self.eps_t0, self.eps_gamma, self.seed, self.burn_in, self.thin,
-                    self.flags)
+                    self.flags, PART_ORDERS[self.part_order])
 
     def eps(self, t: int) -> float:
         return lib().oracle_eps(C.byref(self.c()), t)
@@ -225,6 +231,11 @@ class Chain:
         out = np.zeros(self.cfg.B, dtype=np.int64)
         lib().oracle_part_sizes(C.byref(self.cfg.c()), C.byref(self._state()), _ptr(out))
         return out
+
+    def part_at(self, t: int) -> int:
+        """The part iteration t uses (cyclic, or drawn per Condition 2)."""
+        n_p = self.part_sizes()
+        return int(lib().oracle_part_at(C.byref(self.cfg.c()), t, _ptr(n_p), int(n_p.sum())))
 
     def loglik(self) -> float:
         out = np.zeros(1)

@@ -49,6 +49,12 @@
 
 #define OR_STREAM_W 0u
 #define OR_STREAM_H 1u
+#define OR_STREAM_PART 4u
+
+/* Part order: cyclic (p = t mod B, the experiments' practice), or drawn at
+ * every iteration with probability |part| / N (Condition 2). */
+#define OR_ORDER_CYCLIC 0
+#define OR_ORDER_RANDOM 1
 
 #define OR_PRIOR_EXPONENTIAL 0
 #define OR_PRIOR_GAUSSIAN 1
@@ -64,6 +70,7 @@ typedef struct {
     int64_t burn_in;
     int32_t thin;
     uint32_t flags;
+    int32_t part_order;   /* OR_ORDER_CYCLIC or OR_ORDER_RANDOM */
 } oracle_cfg;
 
 typedef struct {
@@ -392,6 +399,29 @@ int oracle_loglik(const oracle_cfg *c, const oracle_state *s, double *ll)
 /*   c_x = |x_old| + eps (s_p G+_x + |prior'(x_old)|) + sigma R_x            */
 /* (R_x: Box-Muller radius of x's normal) that GPU rounding is measured in.  */
 /* ------------------------------------------------------------------------ */
+/* Part of iteration t.  Random order (Condition 2): one Philox block with
+ * counter (0, 0, t, PART stream) gives u = (2 (r0 >> 9) + 1) 2^-24 in (0,1);
+ * the part is the first p with u N < n_0 + ... + n_p, so part p is drawn
+ * with probability n_p / N (up to the 2^-23 resolution of u) and a part
+ * without entries never.  The comparison is made on integers scaled by 2^24,
+ * exactly.  Without any entry (N = 0) the order is cyclic. */
+int32_t oracle_part_at(const oracle_cfg *c, int64_t t, const int64_t *n_p, int64_t N)
+{
+    if (c->part_order != OR_ORDER_RANDOM || N <= 0) return (int32_t)(t % c->B);
+    const uint32_t ctr[4] = {0u, 0u, (uint32_t)t, OR_STREAM_PART};
+    const uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    const uint64_t scaled_u = 2ull * (uint64_t)(r[0] >> 9) + 1ull;   /* u * 2^24 */
+    const uint64_t lhs = scaled_u * (uint64_t)N;
+    uint64_t cum = 0;
+    for (int32_t p = 0; p < c->B; ++p) {
+        cum += (uint64_t)n_p[p];
+        if (lhs < (cum << 24)) return p;
+    }
+    return c->B - 1;
+}
+
 int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bound_W,
                double *bound_H)
 {
@@ -401,7 +431,7 @@ int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bou
     int64_t I = c->I, J = c->J;
     int32_t K = c->K, B = c->B;
 
-    int64_t *order = NULL, *beg = NULL, *ho_order = NULL, *ho_beg = NULL;
+    int64_t *order = NULL, *beg = NULL, *ho_order = NULL, *ho_beg = NULL, *n_part = NULL;
     rc = bucket_by_part(c, s->row_piece, s->col_piece, s->nnz, s->row, s->col, &order, &beg);
     if (rc) return rc;
     rc = bucket_by_part(c, s->row_piece, s->col_piece, s->nho, s->hrow, s->hcol, &ho_order, &ho_beg);
@@ -418,12 +448,19 @@ int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bou
         goto done;
     }
 
+    n_part = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);
+    if (!n_part) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    for (int32_t q = 0; q < B; ++q) n_part[q] = beg[q + 1] - beg[q];
+
     for (int64_t it = 0; it < n_iter; ++it) {
         int64_t t = s->t;
-        /* Set the step size; pick the part (cyclic order). */
+        /* Set the step size; pick the part. */
         double eps = oracle_eps(c, t);
         double sigma = sqrt(2.0 * eps);
-        int32_t p = (int32_t)(t % B);
+        int32_t p = oracle_part_at(c, t, n_part, s->nnz);
         double scale = part_scale(s->nnz, beg[p + 1] - beg[p]);
         int last = (it == n_iter - 1);
 
@@ -509,6 +546,6 @@ int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bou
 
 done:
     free(gW); free(gH); free(gpW); free(gpH); free(z); free(rad);
-    free(order); free(beg); free(ho_order); free(ho_beg);
+    free(order); free(beg); free(ho_order); free(ho_beg); free(n_part);
     return rc;
 }

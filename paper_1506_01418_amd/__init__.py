@@ -61,12 +61,12 @@ class psgld_options(C.Structure):
                 ("precision", C.c_int32), ("dense_threshold", C.c_double),
                 ("mu_floor", C.c_double), ("row_piece", C.c_void_p), ("col_piece", C.c_void_p),
                 ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32),
-                ("graph_iters", C.c_int32)]
+                ("graph_iters", C.c_int32), ("persistent", C.c_int32), ("part_order", C.c_int32)]
 
 
 class psgld_server_options(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("iters_per_tick", C.c_int32),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("persistent", C.c_int32)]
 
 
 class psgld_job(C.Structure):
@@ -81,6 +81,7 @@ class psgld_job(C.Structure):
 
 
 PSGLD_JOB_QUEUED, PSGLD_JOB_RUNNING, PSGLD_JOB_DONE, PSGLD_JOB_FAILED = 0, 1, 2, 3
+PSGLD_PART_CYCLIC, PSGLD_PART_RANDOM = 0, 1
 
 
 _P = C.c_void_p
@@ -114,6 +115,8 @@ SIGNATURES = {
     "psgld_memory_bytes": ([_P, C.POINTER(_I64)], _ST),
     "psgld_get_stream": ([_P, C.POINTER(_P)], _ST),
     "psgld_last_error": ([_P], C.c_char_p),
+    "psgld_balanced_pieces": ([_I64, _P, C.c_int32, _P], _ST),
+    "psgld_part_at": ([_P, _I64, _P], _ST),
     "psgld_server_create": ([C.POINTER(psgld_server_options), _P], _ST),
     "psgld_server_estimate_bytes": ([C.POINTER(psgld_job), _P], _ST),
     "psgld_server_submit": ([_P, C.POINTER(psgld_job), _P], _ST),
@@ -214,6 +217,24 @@ def psgld_step_batch(ctxs, n_iter, scheds):
     if st != PSGLD_OK:
         bad = next((c for c in ctxs if lib().psgld_last_error(c)), ctxs[0] if ctxs else None)
         _check(st, bad)
+
+
+def psgld_balanced_pieces(weight, B) -> np.ndarray:
+    """Piece of every element, weights balanced over B pieces (host only)."""
+    w = _arr(weight, np.int64)
+    out = np.zeros(len(w), dtype=np.int32)
+    st = lib().psgld_balanced_pieces(len(w), _ptr(w), int(B), _ptr(out))
+    if st != PSGLD_OK:
+        raise PsgldError(st, "psgld_balanced_pieces: need len(weight) >= B >= 1 and weights >= 0")
+    return out
+
+
+def balanced_pieces_for(row, col, I, J, B):
+    """Row and column pieces balancing training entries (+1 per row or
+    column for its own update) over the B pieces."""
+    wr = np.bincount(np.asarray(row), minlength=I).astype(np.int64) + 1
+    wc = np.bincount(np.asarray(col), minlength=J).astype(np.int64) + 1
+    return psgld_balanced_pieces(wr, B), psgld_balanced_pieces(wc, B)
 
 
 def psgld_tune(ctx, candidates, iters, sched: psgld_eps_schedule) -> int:
@@ -344,7 +365,8 @@ class PSGLD:
     def __init__(self, I, J, K, B, beta=2.0, phi=1.0, prior="gaussian", lambda_w=1.0,
                  lambda_h=1.0, mirror=False, seed=0, burn_in=0, thin=1, precision=PSGLD_FP32,
                  dense_threshold=0.3, mu_floor=1e-6, row_piece=None, col_piece=None,
-                 stream: Optional[int] = None, test_flags=0, device=0, graph_iters=0):
+                 stream: Optional[int] = None, test_flags=0, device=0, graph_iters=-1, persistent=0,
+                 part_order="cyclic"):
         self.I, self.J, self.K, self.B = int(I), int(J), int(K), int(B)
         lik = psgld_likelihood(beta, phi)
         pr = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
@@ -357,6 +379,8 @@ class PSGLD:
         opt.col_piece = _ptr(self._pieces[1])
         opt.stream = stream or None
         opt.test_flags, opt.device, opt.graph_iters = test_flags, device, graph_iters
+        opt.persistent = int(bool(persistent))
+        opt.part_order = {"cyclic": PSGLD_PART_CYCLIC, "random": PSGLD_PART_RANDOM}[part_order]
         self.ctx = psgld_create(self.I, self.J, self.K, self.B, lik, pr, opt)
         self.n_heldout = 0
 
@@ -435,6 +459,11 @@ class PSGLD:
 
     def part_sizes(self):
         return psgld_part_sizes(self.ctx, self.B)
+
+    def part_at(self, t):
+        out = C.c_int32()
+        _check(lib().psgld_part_at(self.ctx, int(t), C.byref(out)), self.ctx)
+        return out.value
 
     def get_state(self):
         return psgld_get_state(self.ctx)
@@ -521,8 +550,9 @@ class Server:
     """Serving loop (psgld_server_*): jobs admitted FIFO under an HBM budget
     and stepped together, iters_per_tick iterations per tick."""
 
-    def __init__(self, hbm_budget, max_active=64, iters_per_tick=25, device=0):
-        opt = psgld_server_options(int(hbm_budget), int(max_active), int(iters_per_tick), int(device))
+    def __init__(self, hbm_budget, max_active=64, iters_per_tick=25, device=0, persistent=False):
+        opt = psgld_server_options(int(hbm_budget), int(max_active), int(iters_per_tick), int(device),
+                                   int(bool(persistent)))
         out = C.c_void_p()
         st = lib().psgld_server_create(C.byref(opt), C.byref(out))
         if st != PSGLD_OK:

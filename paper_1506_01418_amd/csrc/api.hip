@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "noise.hpp"
 #include "psgld.h"
 
 using namespace psgld;
@@ -117,11 +118,13 @@ struct psgld_ctx {
 
     // step sizes (eps_t, sigma_t) for t in [eps_base, eps_base + eps_cap)
     float2 *eps_tab = nullptr;
+    int32_t *part_tab = nullptr;      // part of each iteration of the window (random order only)
     int64_t eps_base = 0, eps_cap = 0;
     psgld_eps_schedule eps_sched{};
     // device iteration counter read by captured graphs; clock_host is its
     // value once the enqueued work has run (-1: not set yet)
     int32_t *clock = nullptr;
+    uint32_t *barrier = nullptr;      // grid-wide barrier counter of persistent launches
     int64_t clock_host = -1;
     hipStream_t cap_stream = nullptr;
     // captured runs of iterations, by (first part, ping-pong buffer, length)
@@ -206,6 +209,7 @@ psgld_status ensure_device(psgld_ctx *c)
     psgld_status s = dev_alloc(c, &c->nonfinite, 1);
     if (s) return s;
     if ((s = dev_alloc(c, &c->clock, 1))) return s;
+    if ((s = dev_alloc(c, &c->barrier, 1))) return s;
     const int32_t big = INT_MAX;
     HIPTRY(c, hipMemcpy(c->nonfinite, &big, sizeof(big), hipMemcpyHostToDevice));
     c->device_ready = true;
@@ -231,6 +235,22 @@ int32_t part_of(const psgld_ctx *c, int32_t i, int32_t j)
 float part_scale(const psgld_ctx *c, int32_t p)
 {
     return c->n_p[p] > 0 ? static_cast<float>(static_cast<double>(c->N) / static_cast<double>(c->n_p[p])) : 0.f;
+}
+
+// Part of iteration t: t mod B, or drawn with probability n_p / N (random
+// order; the rule is documented with PSGLD_PART_RANDOM).
+int32_t part_at(const psgld_ctx *c, int64_t t)
+{
+    if (c->opt.part_order != PSGLD_PART_RANDOM || c->N <= 0) return static_cast<int32_t>(t % c->B);
+    const Block4 r = philox4x32_10(0u, 0u, static_cast<uint32_t>(t), 4u, static_cast<uint32_t>(c->opt.seed),
+                                   static_cast<uint32_t>(c->opt.seed >> 32));
+    const uint64_t lhs = (2ull * (r.r[0] >> 9) + 1ull) * static_cast<uint64_t>(c->N);
+    uint64_t cum = 0;
+    for (int32_t p = 0; p < c->B; ++p) {
+        cum += static_cast<uint64_t>(c->n_p[p]);
+        if (lhs < (cum << 24)) return p;
+    }
+    return c->B - 1;
 }
 
 // Builds every part's work schedule for c->sched and uploads it, replacing
@@ -495,8 +515,11 @@ psgld_status ensure_eps_table(psgld_ctx *c, const psgld_eps_schedule *sched, int
         while (cap < 2 * (t_end - t_begin)) cap *= 2;
         drop_graphs(c);
         dev_free(c, c->eps_tab);
+        dev_free(c, c->part_tab);
         c->eps_tab = nullptr;
+        c->part_tab = nullptr;
         psgld_status s = dev_alloc(c, &c->eps_tab, static_cast<size_t>(cap));
+        if (!s && c->opt.part_order == PSGLD_PART_RANDOM) s = dev_alloc(c, &c->part_tab, static_cast<size_t>(cap));
         if (s) return s;
     }
     std::vector<float2> tab(static_cast<size_t>(cap));
@@ -505,6 +528,11 @@ psgld_status ensure_eps_table(psgld_ctx *c, const psgld_eps_schedule *sched, int
         tab[k] = make_float2(static_cast<float>(eps), static_cast<float>(std::sqrt(2.0 * eps)));
     }
     HIPTRY(c, hipMemcpy(c->eps_tab, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice));
+    if (c->part_tab) {
+        std::vector<int32_t> parts(static_cast<size_t>(cap));
+        for (int64_t k = 0; k < cap; ++k) parts[k] = part_at(c, base + k);
+        HIPTRY(c, hipMemcpy(c->part_tab, parts.data(), parts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     c->eps_base = base;
     c->eps_cap = cap;
     c->eps_sched = *sched;
@@ -615,13 +643,13 @@ void account_iteration(psgld_ctx *c, int64_t t)
 {
     if (t < c->opt.burn_in) return;
     if ((t - c->opt.burn_in) % c->opt.thin == 0) c->n_kept++;
-    if (c->n_ho > 0) c->part_visits[t % c->B]++;
+    if (c->n_ho > 0) c->part_visits[part_at(c, t)]++;
 }
 
 // Iterations per captured graph (0 = do not capture).
 int64_t graph_length(const psgld_ctx *c)
 {
-    if (c->opt.graph_iters < 0) return 0;
+    if (c->opt.graph_iters < 0 || c->opt.part_order == PSGLD_PART_RANDOM) return 0;
     if (c->opt.graph_iters > 0) return c->opt.graph_iters;
     return static_cast<int64_t>(c->B) * ((32 + c->B - 1) / c->B);
 }
@@ -695,6 +723,7 @@ psgld_status sync_job_desc(psgld_ctx *c)
     d.prior_kind = c->prior.kind;
     d.flags = c->opt.test_flags;
     d.eps_tab = c->eps_tab - c->eps_base;
+    d.part_tab = c->part_tab ? c->part_tab - c->eps_base : nullptr;
     d.clock = c->clock;
     d.cur_phase = (c->cur ^ static_cast<int>(c->t & 1)) & 1;
     d.burn_in = static_cast<int32_t>(std::min<int64_t>(c->opt.burn_in, INT32_MAX));
@@ -721,6 +750,50 @@ psgld_status sync_job_desc(psgld_ctx *c)
     HIPTRY(c, hipMemcpy(c->job_desc, &d, sizeof(d), hipMemcpyHostToDevice));
     c->job_host = d;
     c->job_valid = true;
+    return PSGLD_OK;
+}
+
+// n_iter iterations of coordinate-stored contexts of one kernel variant in
+// cooperative launches of up to kPersistentIters iterations, then the host
+// record of those iterations.  Step-size tables must cover them.
+constexpr int64_t kPersistentIters = 256;
+
+psgld_status step_persistent(psgld_ctx *const *ctxs, int n, int64_t n_iter, hipStream_t stream)
+{
+    psgld_ctx *c0 = ctxs[0];
+    for (int j = 0; j < n; ++j) {
+        psgld_ctx *c = ctxs[j];
+        psgld_status s = sync_job_desc(c);
+        if (s) return s;
+        if (c->clock_host != c->t) {
+            HIPTRY(c, launch_set_clock(c->clock, static_cast<int32_t>(c->t), stream));
+            c->clock_host = c->t;
+        }
+    }
+    for (int first = 0; first < n; first += kMaxBatch) {
+        const int cnt = std::min(kMaxBatch, n - first);
+        BatchArgs b{};
+        b.n = cnt;
+        std::vector<int32_t *> clocks;
+        for (int q = 0; q < cnt; ++q) {
+            psgld_ctx *c = ctxs[first + q];
+            b.jobs[q] = c->job_desc;
+            b.wg_first[q + 1] = b.wg_first[q] + c->max_tasks;
+            clocks.push_back(c->clock);
+        }
+        for (int64_t done = 0; done < n_iter; done += kPersistentIters) {
+            const int chunk = static_cast<int>(std::min(kPersistentIters, n_iter - done));
+            HIPTRY(c0, launch_sparse_persistent(b, chunk, c0->lik_kind, c0->lpg, c0->qpl, 0, c0->barrier, stream));
+            HIPTRY(c0, launch_advance_clocks(clocks.data(), cnt, chunk, stream));
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        psgld_ctx *c = ctxs[j];
+        for (int64_t k = 0; k < n_iter; ++k) account_iteration(c, c->t + k);
+        c->cur ^= static_cast<int>(n_iter & 1);
+        c->t += n_iter;
+        c->clock_host = c->t;
+    }
     return PSGLD_OK;
 }
 
@@ -753,6 +826,9 @@ void psgld_default_options(psgld_options *opt)
     opt->stream = nullptr;
     opt->test_flags = 0;
     opt->device = 0;
+    opt->graph_iters = -1;
+    opt->persistent = 0;
+    opt->part_order = PSGLD_PART_CYCLIC;
 }
 
 psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgld_likelihood *lik,
@@ -782,6 +858,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (!(o.mu_floor > 0.0)) return bad("mu_floor must be > 0");
     if (o.precision != PSGLD_FP32 && o.precision != PSGLD_BF16_DENSE) return bad("unknown precision");
     if (o.device < 0) return bad("device must be >= 0");
+    if (o.part_order != PSGLD_PART_CYCLIC && o.part_order != PSGLD_PART_RANDOM) return bad("unknown part order");
 
     psgld_ctx *c = new (std::nothrow) psgld_ctx();
     if (!c) {
@@ -1121,6 +1198,10 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     if (n_iter == 0) return PSGLD_OK;
     HIPTRY(c, hipSetDevice(c->opt.device));
     if ((s = ensure_eps_table(c, sched, c->t, c->t + n_iter))) return s;
+    if (c->opt.persistent && c->dblocks_host.empty()) {
+        psgld_ctx *one[1] = {c};
+        return step_persistent(one, 1, n_iter, c->stream);
+    }
     const int64_t L = graph_length(c);
     while (n_iter > 0) {
         if (L > 0 && n_iter >= L) {
@@ -1137,7 +1218,7 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
             c->t += L;
             n_iter -= L;
         } else {
-            HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>(c->t % c->B), c->cur, nullptr,
+            HIPTRY(c, enqueue_iteration(c, part_at(c, c->t), c->cur, nullptr,
                                         static_cast<int32_t>(c->t), true, c->stream));
             account_iteration(c, c->t);
             c->cur ^= 1;
@@ -1188,6 +1269,35 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
             c->clock_host = c->t;
         }
     }
+    bool persistent = false;
+    for (int32_t j = 0; j < n; ++j)
+        if (batched[j]) persistent = true;
+    for (int32_t j = 0; j < n; ++j)
+        if (batched[j] && !ctxs[j]->opt.persistent) persistent = false;
+    if (persistent) {
+        // one cooperative launch per (variant, iteration count) group
+        std::map<std::tuple<int, int, int, int64_t>, std::vector<psgld_ctx *>> groups;
+        for (int32_t j = 0; j < n; ++j)
+            if (batched[j])
+                groups[std::make_tuple(ctxs[j]->lpg, ctxs[j]->qpl, ctxs[j]->lik_kind, n_iter[j])].push_back(ctxs[j]);
+        for (auto &g : groups) {
+            psgld_status s = step_persistent(g.second.data(), static_cast<int>(g.second.size()), std::get<3>(g.first),
+                                             stream);
+            if (s) return s;
+        }
+        for (int32_t j = 0; j < n; ++j) {
+            psgld_ctx *c = ctxs[j];
+            if (batched[j] || n_iter[j] == 0) continue;
+            for (int64_t k = 0; k < n_iter[j]; ++k) {
+                HIPTRY(c, enqueue_iteration(c, part_at(c, c->t), c->cur, nullptr,
+                                            static_cast<int32_t>(c->t), true, stream));
+                account_iteration(c, c->t);
+                c->cur ^= 1;
+                c->t += 1;
+            }
+        }
+        return PSGLD_OK;
+    }
     for (int64_t k = 0; k < max_n; ++k) {
         // one launch per kernel variant (lanes per group, quads per lane,
         // likelihood) and 64 contexts
@@ -1212,12 +1322,12 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
                 HIPTRY(c0, launch_sparse_batch(b, std::get<2>(g.first), std::get<0>(g.first), std::get<1>(g.first), stream));
             }
         }
-        if (!clocks.empty()) HIPTRY(c0, launch_advance_clocks(clocks.data(), static_cast<int>(clocks.size()), stream));
+        if (!clocks.empty()) HIPTRY(c0, launch_advance_clocks(clocks.data(), static_cast<int>(clocks.size()), 1, stream));
         for (int32_t j = 0; j < n; ++j) {
             if (k >= n_iter[j]) continue;
             psgld_ctx *c = ctxs[j];
             if (!batched[j])
-                HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>(c->t % c->B), c->cur, nullptr,
+                HIPTRY(c, enqueue_iteration(c, part_at(c, c->t), c->cur, nullptr,
                                             static_cast<int32_t>(c->t), true, stream));
             account_iteration(c, c->t);
             c->cur ^= 1;
@@ -1266,7 +1376,7 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
                 c->cur = cur0;
                 HIPTRY(c, hipEventRecord(e0, c->stream));
                 for (int32_t it = 0; it < iters; ++it)
-                    HIPTRY(c, enqueue_iteration(c, static_cast<int32_t>((c->t + it) % c->B), (cur0 + it) & 1,
+                    HIPTRY(c, enqueue_iteration(c, part_at(c, c->t + it), (cur0 + it) & 1,
                                                 nullptr, static_cast<int32_t>(c->t + it), false, c->stream));
                 HIPTRY(c, hipEventRecord(e1, c->stream));
                 HIPTRY(c, hipEventSynchronize(e1));
@@ -1541,6 +1651,38 @@ void psgld_destroy(psgld_ctx *c)
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
+}
+
+psgld_status psgld_part_at(psgld_ctx *c, int64_t t, int32_t *part)
+{
+    if (!c || !part || t < 0) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load data first");
+    *part = part_at(c, t);
+    return PSGLD_OK;
+}
+
+psgld_status psgld_balanced_pieces(int64_t n, const int64_t *weight, int32_t B, int32_t *piece)
+{
+    if (n < 1 || B < 1 || n < B || !weight || !piece) return PSGLD_E_ARG;
+    for (int64_t m = 0; m < n; ++m)
+        if (weight[m] < 0) return PSGLD_E_ARG;
+    std::vector<int64_t> order(static_cast<size_t>(n));
+    std::iota(order.begin(), order.end(), int64_t{0});
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return weight[a] > weight[b]; });
+    // least-loaded piece first (lowest index on ties): a heap of (load, piece)
+    std::vector<std::pair<int64_t, int32_t>> heap;
+    for (int32_t b = 0; b < B; ++b) heap.emplace_back(0, b);
+    auto later = [](const std::pair<int64_t, int32_t> &x, const std::pair<int64_t, int32_t> &y) { return x > y; };
+    std::make_heap(heap.begin(), heap.end(), later);
+    for (int64_t m : order) {
+        std::pop_heap(heap.begin(), heap.end(), later);
+        auto &top = heap.back();
+        piece[m] = top.second;
+        top.first += weight[m];
+        std::push_heap(heap.begin(), heap.end(), later);
+    }
+    return PSGLD_OK;
 }
 
 psgld_status psgld_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,

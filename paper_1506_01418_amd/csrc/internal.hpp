@@ -143,6 +143,7 @@ struct JobDesc {
     int32_t mirror, prior_kind;
     uint32_t flags;
     const float2 *eps_tab;            // indexed by the global iteration
+    const int32_t *part_tab;          // part of each global iteration, or null (t mod B)
     const int32_t *clock;
     int32_t cur_phase;
     int32_t burn_in, thin, has_heldout;
@@ -165,8 +166,14 @@ struct BatchArgs {
 
 hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lanes_per_group, int quads_per_lane,
                                hipStream_t stream);
-// *clocks[j] += 1 for j < n.
-hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream);
+// *clocks[j] += delta for j < n.
+hipError_t launch_advance_clocks(int32_t *const *clocks, int n, int delta, hipStream_t stream);
+// n_iter iterations of the batch in one cooperative launch of `grid`
+// work-groups (<= 0: as many as the device holds at once, capped by the
+// work), with `barrier` (one device word, reset by the launch) as the
+// grid-wide barrier counter; the clocks are not advanced.
+hipError_t launch_sparse_persistent(const BatchArgs &b, int n_iter, int lik, int lanes_per_group, int quads_per_lane,
+                                    int grid, uint32_t *barrier, hipStream_t stream);
 
 // Launches one sparse iteration with the kernel variant chosen for (K, lik).
 hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lanes_per_group, int quads_per_lane,

@@ -143,6 +143,7 @@ psgld_status load_job(psgld_server *srv, Job *j)
     o.stream = srv->stream;
     o.device = srv->opt.device;
     o.graph_iters = -1;
+    o.persistent = srv->opt.persistent ? 1 : 0;
     psgld_status st = psgld_create(s.I, s.J, s.K, s.B, &s.lik, &s.prior, &o, &j->ctx);
     if (st) {
         j->err = psgld_last_error(nullptr);

@@ -398,23 +398,13 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_iter_kernel(SparseIterAr
     sparse_task<LPG, QPL, LIK>(a, iter_scalars(a.clk), blockIdx.x);
 }
 
-// Several contexts in one launch: the work-group finds its context, reads
-// the context's clock, and runs task (blockIdx - first) of the current part
-// with exactly the arguments a single-context launch would pass.
+// Task `task` of context d at iteration t, with exactly the arguments a
+// single-context launch would pass.  Returns without work when the current
+// part has fewer tasks.
 template <int LPG, int QPL, int LIK>
-__global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b)
+__device__ __forceinline__ void job_task(const JobDesc &d, int32_t t, int task)
 {
-    const int wg = blockIdx.x;
-    int lo = 0, hi = b.n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (b.wg_first[mid] <= wg) lo = mid;
-        else hi = mid;
-    }
-    const JobDesc &d = *b.jobs[lo];
-    const int32_t t = *d.clock;
-    const int p = t % d.B;
-    const int task = wg - b.wg_first[lo];
+    const int p = d.part_tab ? d.part_tab[t] : t % d.B;
     if (task >= d.n_tasks[p]) return;
     const int cur = (t + d.cur_phase) & 1;
     constexpr int Q = kBlockThreads / LPG;
@@ -459,14 +449,114 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b
     sparse_task<LPG, QPL, LIK>(a, it, task);
 }
 
+// The context of virtual work-group v: wg_first[j] <= v < wg_first[j + 1].
+__device__ __forceinline__ int job_of(const int32_t *wg_first, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wg_first[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Several contexts in one launch: the work-group finds its context, reads
+// the context's clock and runs its task of the current part.
+template <int LPG, int QPL, int LIK>
+__global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b)
+{
+    const int j = job_of(b.wg_first, b.n, blockIdx.x);
+    const JobDesc &d = *b.jobs[j];
+    job_task<LPG, QPL, LIK>(d, *d.clock, blockIdx.x - b.wg_first[j]);
+}
+
+// n_iter iterations of the contexts in one cooperative launch.  The grid is
+// at most what the device holds at once, so every work-group is resident;
+// each strides over the virtual work-groups of all contexts (context j's
+// tasks of its current part), then waits at a grid-wide barrier, which also
+// orders the iteration's factor writes before the next iteration's reads.
+// Every work-group runs the same n_iter barriers.
+//
+// The barrier is a counter that starts at 0 for the launch: after the k-th
+// iteration each work-group waits (thread 0, with a short sleep) until the
+// counter reaches (k + 1) * gridDim.x.  Its increment is an agent-scope
+// release, after every thread's stores have completed (vmcnt 0) and a
+// work-group barrier; the wait polls with relaxed loads and ends with one
+// agent-scope acquire fence, so the next iteration sees all factor writes of
+// this one on every XCD.  All work-groups are resident (cooperative launch),
+// so every wait ends.
+template <int LPG, int QPL, int LIK>
+__global__ __launch_bounds__(kBlockThreads) void sparse_persistent_kernel(BatchArgs b, int32_t n_iter,
+                                                                          uint32_t *barrier)
+{
+    __shared__ int ready;
+    const int total = b.wg_first[b.n];
+    for (int k = 0; k < n_iter; ++k) {
+        for (int v = blockIdx.x; v < total; v += gridDim.x) {
+            const int j = job_of(b.wg_first, b.n, v);
+            const JobDesc &d = *b.jobs[j];
+            job_task<LPG, QPL, LIK>(d, *d.clock + k, v - b.wg_first[j]);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's stores have reached L2
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t target = static_cast<uint32_t>(k + 1) * gridDim.x;
+            __hip_atomic_fetch_add(barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            while (__hip_atomic_load(barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+                __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            ready = 1;
+        }
+        __syncthreads();
+    }
+    (void)ready;
+}
+
+__global__ void reset_barrier_kernel(uint32_t *barrier)
+{
+    if (threadIdx.x == 0) *barrier = 0u;
+}
+
 struct ClockList {
     int32_t *clocks[kMaxBatch];
     int32_t n;
+    int32_t delta;
 };
 
 __global__ void advance_clocks_kernel(ClockList l)
 {
-    if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += 1;
+    if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += l.delta;
+}
+
+template <int LPG, int QPL>
+hipError_t launch_persistent_lpg(const BatchArgs &b, int n_iter, int lik, int grid, uint32_t *barrier,
+                                 hipStream_t stream)
+{
+    void *args[] = {const_cast<BatchArgs *>(&b), &n_iter, &barrier};
+    const void *f;
+    switch (lik) {
+    case LIK_GAUSS: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_GAUSS>); break;
+    case LIK_POISSON: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_POISSON>); break;
+    case LIK_HALF: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_HALF>); break;
+    case LIK_GAMMA: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_GAMMA>); break;
+    default: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_GENERAL>); break;
+    }
+    if (grid <= 0) {
+        // as many work-groups as the device holds at once, and no more than there is work
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlockThreads, 0);
+        if (e != hipSuccess) return e;
+        grid = std::min(per_cu * prop.multiProcessorCount, b.wg_first[b.n]);
+    }
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(reset_barrier_kernel, dim3(1), dim3(64), 0, stream, barrier);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(f, dim3(static_cast<unsigned>(grid)), dim3(kBlockThreads), args, 0, stream);
 }
 
 template <int LPG, int QPL>
@@ -541,10 +631,35 @@ hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, int qpl, hi
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_advance_clocks(int32_t *const *clocks, int n, hipStream_t stream)
+hipError_t launch_sparse_persistent(const BatchArgs &b, int n_iter, int lik, int lpg, int qpl, int grid,
+                                    uint32_t *barrier, hipStream_t stream)
+{
+    if (b.n <= 0 || b.n > kMaxBatch || n_iter <= 0) return b.n > kMaxBatch ? hipErrorInvalidValue : hipSuccess;
+    if (qpl == 1) {
+        switch (lpg) {
+        case 1: return launch_persistent_lpg<1, 1>(b, n_iter, lik, grid, barrier, stream);
+        case 2: return launch_persistent_lpg<2, 1>(b, n_iter, lik, grid, barrier, stream);
+        case 4: return launch_persistent_lpg<4, 1>(b, n_iter, lik, grid, barrier, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (qpl == 2) {
+        switch (lpg) {
+        case 4: return launch_persistent_lpg<4, 2>(b, n_iter, lik, grid, barrier, stream);
+        case 8: return launch_persistent_lpg<8, 2>(b, n_iter, lik, grid, barrier, stream);
+        case 16: return launch_persistent_lpg<16, 2>(b, n_iter, lik, grid, barrier, stream);
+        case 32: return launch_persistent_lpg<32, 2>(b, n_iter, lik, grid, barrier, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_advance_clocks(int32_t *const *clocks, int n, int delta, hipStream_t stream)
 {
     for (int first = 0; first < n; first += kMaxBatch) {
         ClockList l{};
+        l.delta = delta;
         l.n = std::min(kMaxBatch, n - first);
         for (int j = 0; j < l.n; ++j) l.clocks[j] = clocks[first + j];
         hipLaunchKernelGGL(advance_clocks_kernel, dim3(1), dim3(kMaxBatch), 0, stream, l);

@@ -12,9 +12,10 @@ TOL_FP32 = 1e-5
 TOL_BF16 = 2e-2
 
 
-def oracle_config(wl, flags=0):
+def oracle_config(wl, flags=0, part_order="cyclic"):
     cfg = oracle.Config(**wl.fit_kwargs())
     cfg.flags = flags
+    cfg.part_order = part_order
     return cfg
 
 
@@ -33,7 +34,7 @@ def step_parity(wl, steps_before=0, flags=0, sampler=None, dense=False, **overri
     if steps_before:
         s.step(steps_before, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     Wg, Hg = s.factors()
-    cfg = oracle_config(wl, flags)
+    cfg = oracle_config(wl, flags, overrides.get("part_order", "cyclic"))
     ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol,
                       row_piece=overrides.get("row_piece"), col_piece=overrides.get("col_piece"))
     ch.set_state(Wg, Hg, s.iteration())

@@ -31,6 +31,7 @@ def test_every_declared_function_is_exported():
 def test_default_options():
     o = pkg.psgld_default_options()
     assert o.thin == 1 and o.dense_threshold == 0.3 and o.mu_floor == 1e-6 and o.device == 0
+    assert o.graph_iters == -1 and o.persistent == 0 and o.part_order == pkg.PSGLD_PART_CYCLIC
 
 
 @pytest.mark.parametrize("I,J,K,B,beta,phi,lw,msg", [
@@ -79,3 +80,43 @@ def test_load_validates_on_host_before_device():
     assert e.value.status == pkg.PSGLD_E_ARG
     s.close()
     g.close()
+
+
+def test_balanced_pieces_lpt():
+    """Heaviest first into the least-loaded piece: no piece empty, loads
+    within the largest single weight of each other, deterministic."""
+    rng = np.random.default_rng(5)
+    w = (rng.zipf(1.3, 5000) % 20000).astype(np.int64)
+    for B in (1, 3, 32, 64):
+        p = pkg.psgld_balanced_pieces(w, B)
+        loads = np.bincount(p, weights=w, minlength=B)
+        assert np.all(np.bincount(p, minlength=B) > 0)
+        assert loads.max() - loads.min() <= w.max()
+        assert np.array_equal(p, pkg.psgld_balanced_pieces(w, B))
+    # equal weights: sizes differ by at most one
+    p = pkg.psgld_balanced_pieces(np.ones(103, np.int64), 10)
+    sizes = np.bincount(p, minlength=10)
+    assert sizes.max() - sizes.min() <= 1
+    with pytest.raises(pkg.PsgldError):
+        pkg.psgld_balanced_pieces(np.ones(3, np.int64), 4)
+    with pytest.raises(pkg.PsgldError):
+        pkg.psgld_balanced_pieces(np.array([1, -1, 2], np.int64), 2)
+
+
+def test_balanced_pieces_even_out_zipf_parts():
+    """On Zipf-skewed ratings the balanced pieces give parts of more equal
+    size than contiguous pieces (smaller spread of s_p = N / n_p)."""
+    import oracle
+    wl = workloads_small_zipf()
+    rp, cp = pkg.balanced_pieces_for(wl.row, wl.col, wl.I, wl.J, wl.B)
+    def part_sizes(rp, cp):
+        part = (cp[wl.col] - rp[wl.row]) % wl.B
+        return np.bincount(part, minlength=wl.B)
+    contiguous = part_sizes(oracle.partition(wl.I, wl.B), oracle.partition(wl.J, wl.B))
+    balanced = part_sizes(rp, cp)
+    assert balanced.max() / balanced.min() < contiguous.max() / contiguous.min()
+
+
+def workloads_small_zipf():
+    import workloads
+    return workloads.random_sparse(3000, 800, 80_000, 8, 8, zipf_a=1.2, data_seed=17, chain_seed=18)

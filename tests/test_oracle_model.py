@@ -404,3 +404,63 @@ def test_resume_is_bit_identical():
     c.run(6)
     for x, y in [(a.W, c.W), (a.H, c.H), (a.sumW, c.sumW), (a.sumH2, c.sumH2), (a.ho_sum, c.ho_sum)]:
         assert np.array_equal(x, y)
+
+
+# ------------------------------------------------- Condition 2: random part order
+def _skewed_chain(order, seed=3):
+    """B = 4 pieces chosen so the four parts hold very different numbers of
+    entries (one of them none)."""
+    I, J, K, B = 12, 12, 2, 4
+    rp = np.repeat(np.arange(B), 3).astype(np.int32)
+    cp = rp.copy()
+    rng = np.random.default_rng(seed)
+    want = {0: 30, 1: 12, 2: 0, 3: 6}        # entries per part
+    row, col = [], []
+    for p, n in want.items():
+        cells = [(i, j) for i in range(I) for j in range(J) if (rp[i] + p) % B == cp[j]]
+        pick = rng.choice(len(cells), size=n, replace=False)
+        row += [cells[k][0] for k in pick]
+        col += [cells[k][1] for k in pick]
+    row, col = np.array(row, np.int32), np.array(col, np.int32)
+    val = rng.gamma(2.0, 1.0, len(row))
+    W0, H0 = rng.gamma(2.0, 0.5, (I, K)), rng.gamma(2.0, 0.5, (K, J))
+    cfg = oracle.Config(I=I, J=J, K=K, B=B, beta=2.0, phi=1.0, eps_a=1e-2, eps_gamma=0.0, seed=77,
+                        flags=oracle.FLAG_NOISE_OFF | oracle.FLAG_FREEZE_H, part_order=order)
+    return oracle.Chain(cfg, row, col, val, W0, H0, row_piece=rp, col_piece=cp), row, col, val, W0, H0, cfg, rp, cp
+
+
+def test_random_part_frequencies_follow_condition2():
+    """Condition 2: p(Pi) = |Pi| / N.  Over many iterations the drawn parts'
+    frequencies match n_p / N (chi-square), and the empty part never occurs."""
+    ch = _skewed_chain("random")[0]
+    n_p = ch.part_sizes()
+    assert list(n_p) == [30, 12, 0, 6]
+    draws = np.array([ch.part_at(t) for t in range(60_000)])
+    cnt = np.bincount(draws, minlength=4)
+    assert cnt[2] == 0
+    expected = n_p / n_p.sum() * len(draws)
+    m = expected > 0
+    chi2 = float(np.sum((cnt[m] - expected[m]) ** 2 / expected[m]))
+    assert chi2 < 16.3, (cnt, expected)    # 3 degrees of freedom, p < 0.001
+    # the cyclic order is t mod B
+    cyc = _skewed_chain("cyclic")[0]
+    assert [cyc.part_at(t) for t in range(9)] == [t % 4 for t in range(9)]
+
+
+def test_random_order_steps_use_the_drawn_part():
+    """A noise-off step at iteration t depends exactly on the entries of the
+    part drawn for t: perturbing an entry changes W iff it lies in that part."""
+    ch0, row, col, val, W0, H0, cfg, rp, cp = _skewed_chain("random")
+    for t in range(6):
+        p = ch0.part_at(t)
+        base = oracle.Chain(cfg, row, col, val, W0, H0, row_piece=rp, col_piece=cp)
+        base.t = t
+        base.run(1)
+        for e in range(len(row)):
+            v2 = val.copy()
+            v2[e] += 1.0
+            ch = oracle.Chain(cfg, row, col, v2, W0, H0, row_piece=rp, col_piece=cp)
+            ch.t = t
+            ch.run(1)
+            inside = (rp[row[e]] + p) % 4 == cp[col[e]]
+            assert (not np.array_equal(ch.W, base.W)) == inside, (t, e)
