@@ -353,6 +353,10 @@ def main():
     s.sync()
     rmse2 = s.heldout_rmse() if args.steps > wl.burn_in else None
     avg_ms = float(durs.mean())
+    pre = durs[: min(args.steps, wl.burn_in)]
+    post = durs[min(args.steps, wl.burn_in):]
+    print(f"[bench] launch average before burn-in {pre.mean() * 1e3:.2f} us"
+          + (f", after {post.mean() * 1e3:.2f} us" if len(post) else ""), file=sys.stderr, flush=True)
     if dense:
         cells_p = dense_part_cells(wl)
         bf = np.array([dense_algorithmic(wl, cells_p, ho_p, t, parts[t]) for t in range(args.steps)],

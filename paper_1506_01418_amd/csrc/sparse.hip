@@ -233,15 +233,33 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, const IterS
                                             const float4 (&x)[QPL], const float4 (&g)[QPL], int lane)
 {
     if (side == 0 && it.do_heldout) {
+        // held-out cells of the row in this block, a batch at a time: the
+        // batch's records, partner loads and FP64 sums are all in flight
+        // together (records past the row's last cell are clamped to it and
+        // their sums skipped)
+        constexpr int U = kBatch<QPL>;
         const float *other_lane = a.x_old[1] + 4 * lane;
         const int hb = a.ho_ptr[item], he = a.ho_ptr[item + 1];
-        for (int h = hb; h < he; ++h) {
-            const HeldEntry c = a.ho_ent[h];
-            float d = dot4(x[0], load4(other_lane + c.off));
+        for (int h0 = hb; h0 < he; h0 += U) {
+            HeldEntry c[U];
 #pragma unroll
-            for (int m = 1; m < QPL; ++m) d += dot4(x[m], load4(other_lane + c.off + 4 * m * LPG));
-            const float mu = group_sum<LPG>(d);
-            if (lane == 0) a.ho_sum[c.slot] += static_cast<double>(mu);
+            for (int u = 0; u < U; ++u) c[u] = a.ho_ent[min(h0 + u, he - 1)];
+            float mu[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                mu[u] = dot4(x[0], load4(other_lane + c[u].off));
+#pragma unroll
+                for (int m = 1; m < QPL; ++m) mu[u] += dot4(x[m], load4(other_lane + c[u].off + 4 * m * LPG));
+            }
+            group_sum_n<LPG, U>(mu);
+            if (lane == 0) {
+                double prev[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) prev[u] = h0 + u < he ? a.ho_sum[c[u].slot] : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (h0 + u < he) a.ho_sum[c[u].slot] = prev[u] + static_cast<double>(mu[u]);
+            }
         }
     }
     const bool frozen = (a.flags & (side == 0 ? PSGLD_TEST_FREEZE_W : PSGLD_TEST_FREEZE_H)) != 0;
