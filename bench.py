@@ -32,6 +32,13 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 METRIC = "observed-entry SGLD updates/s at matched held-out RMSE; served-job p50/p99"
+# The paper's own figures for the same metric and workload shape (another
+# GPU: a GeForce GT 750M), as lower bounds of observed-entry updates/s:
+# Poisson NMF 1024 x 1024, K = 32, B = 32, 10,000 samples in under 15 s
+# (Section 4.2.1); the 256 x 256, K = 8, B = 8 spectrum, 10,000 samples in
+# 3.5 s (Section 4.2.2, stood in for by synthetic Poisson NMF data).
+PAPER_UPDATES_PER_S = {"paper_poisson_1024": 10_000 * 1024 * 1024 / 32 / 15.0,
+                       "paper_spectrum_256": 10_000 * 256 * 256 / 8 / 3.5}
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 
@@ -152,6 +159,19 @@ def make_workload(name):
                                       zipf_a=1.1, data_seed=1004, chain_seed=2004, name=name)
         wl.thin = 10
         return wl
+    if name == "paper_poisson_1024":
+        # the paper's synthetic Poisson NMF, fully observed.  Its step size
+        # (0.01 / t)^0.51 diverges within a few iterations under this
+        # gradient scaling (N / |part| times the part's sum), so the step
+        # constant comes from the stability rule with the paper's decay
+        wl = workloads.dense_poisson(I=1024, J=1024, K=32, B=32, heldout=0.0, data_seed=1010,
+                                     chain_seed=2010, T=10_000, burn_in=5_000, thin=10, name=name)
+        wl.eps_a = workloads.step_scale(wl.row, wl.col, wl.val, wl.I, wl.J, wl.beta, wl.phi)
+        return wl
+    if name == "paper_spectrum_256":
+        return workloads.dense_poisson(I=256, J=256, K=8, B=8, heldout=0.0, data_seed=1011,
+                                       chain_seed=2011, T=10_000, burn_in=5_000, thin=10,
+                                       eps_a=1e-3, eps_t0=1.0, eps_gamma=0.51, name=name)
     if name == "dense_poisson_256":
         return workloads.dense_poisson()
     if name == "sparse_ratings_small":
@@ -337,7 +357,7 @@ def main():
     parts = [s.part_at(t) for t in range(args.steps)]
     entries = int(sum(n_p[p] for p in parts))
     value = entries / (elapsed_ms * 1e-3)
-    rmse = s.heldout_rmse() if args.steps > wl.burn_in else None
+    rmse = s.heldout_rmse() if args.steps > wl.burn_in and len(wl.hrow) else None
     print(f"[bench] pass 1: {args.steps} iterations in {elapsed_ms:.3f} ms, "
           f"{value:.4g} updates/s, held-out RMSE {rmse}", file=sys.stderr, flush=True)
 
@@ -351,7 +371,8 @@ def main():
         ev.record(evs[2 * t + 1], stream)
     durs = np.array([ev.elapsed_ms(evs[2 * t], evs[2 * t + 1]) for t in range(args.steps)])
     s.sync()
-    rmse2 = s.heldout_rmse() if args.steps > wl.burn_in else None
+    rmse2 = s.heldout_rmse() if args.steps > wl.burn_in and len(wl.hrow) else None
+    loglik = s.log_likelihood()
     avg_ms = float(durs.mean())
     pre = durs[: min(args.steps, wl.burn_in)]
     post = durs[min(args.steps, wl.burn_in):]
@@ -396,13 +417,14 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": value / PAPER_UPDATES_PER_S[wl.name] if wl.name in PAPER_UPDATES_PER_S else None,
         "dtype": "bf16+f32" if dense and args.precision == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
                    "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
-                   "heldout_rmse": rmse, "entries_per_group": chosen, "dense": dense,
+                   "heldout_rmse": rmse, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": dense,
                    "precision": args.precision if dense else "f32", "parallelism": "single-gpu",
                    "part_order": args.part_order, "balanced_pieces": bool(pieces),
                    "launch": "persistent" if args.persistent and not dense else

@@ -121,11 +121,16 @@ typedef struct {
                                  iterations; no graph); 0 = off */
     int32_t part_order;       /* PSGLD_PART_CYCLIC (default) or PSGLD_PART_RANDOM;
                                  random order is never captured into graphs */
+    int32_t dense_min_cols;   /* blocks narrower than this run as coordinates
+                                 even when dense (default 256: one dense
+                                 work-group's width; narrower tiles measured
+                                 slower than the coordinate kernel) */
 } psgld_options;
 
 /* Fills *opt with the defaults: seed 0, burn_in 0, thin 1, FP32,
  * dense_threshold 0.3, mu_floor 1e-6, contiguous pieces, own stream,
- * no test flags, device 0, graph_iters -1, persistent 0, cyclic part order. */
+ * no test flags, device 0, graph_iters -1, persistent 0, cyclic part order,
+ * dense_min_cols 256. */
 void psgld_default_options(psgld_options *opt);
 
 /* Creates a context for an I x J matrix, rank K (1..256), B x B blocks
@@ -323,8 +328,8 @@ typedef struct {
  * psgld_load_dense (row == NULL, dense != NULL, mask may be NULL); held-out
  * cells as for psgld_load_heldout (n_heldout may be 0); W0 (I x K) and H0
  * (K x J) as for psgld_set_factors.  The job runs n_iter >= 1 iterations of
- * schedule sched with the given seed, burn-in, thinning, precision and dense
- * threshold (other options at their defaults). */
+ * schedule sched with the given seed, burn-in, thinning, precision, dense
+ * threshold and dense width (other options at their defaults). */
 typedef struct {
     int64_t I, J;
     int32_t K, B;
@@ -335,6 +340,7 @@ typedef struct {
     int32_t thin;
     int32_t precision;
     double dense_threshold;
+    int32_t dense_min_cols;   /* as options.dense_min_cols; 0 = its default */
     psgld_eps_schedule sched;
     int64_t n_iter;
     int64_t nnz;

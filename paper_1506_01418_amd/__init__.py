@@ -61,7 +61,8 @@ class psgld_options(C.Structure):
                 ("precision", C.c_int32), ("dense_threshold", C.c_double),
                 ("mu_floor", C.c_double), ("row_piece", C.c_void_p), ("col_piece", C.c_void_p),
                 ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32),
-                ("graph_iters", C.c_int32), ("persistent", C.c_int32), ("part_order", C.c_int32)]
+                ("graph_iters", C.c_int32), ("persistent", C.c_int32), ("part_order", C.c_int32),
+                ("dense_min_cols", C.c_int32)]
 
 
 class psgld_server_options(C.Structure):
@@ -73,7 +74,8 @@ class psgld_job(C.Structure):
     _fields_ = [("I", C.c_int64), ("J", C.c_int64), ("K", C.c_int32), ("B", C.c_int32),
                 ("lik", psgld_likelihood), ("prior", psgld_prior), ("seed", C.c_uint64),
                 ("burn_in", C.c_int64), ("thin", C.c_int32), ("precision", C.c_int32),
-                ("dense_threshold", C.c_double), ("sched", psgld_eps_schedule), ("n_iter", C.c_int64),
+                ("dense_threshold", C.c_double), ("dense_min_cols", C.c_int32),
+                ("sched", psgld_eps_schedule), ("n_iter", C.c_int64),
                 ("nnz", C.c_int64), ("row", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
                 ("dense", C.c_void_p), ("mask", C.c_void_p), ("n_heldout", C.c_int64),
                 ("hrow", C.c_void_p), ("hcol", C.c_void_p), ("hval", C.c_void_p),
@@ -366,7 +368,7 @@ class PSGLD:
                  lambda_h=1.0, mirror=False, seed=0, burn_in=0, thin=1, precision=PSGLD_FP32,
                  dense_threshold=0.3, mu_floor=1e-6, row_piece=None, col_piece=None,
                  stream: Optional[int] = None, test_flags=0, device=0, graph_iters=-1, persistent=0,
-                 part_order="cyclic"):
+                 part_order="cyclic", dense_min_cols=256):
         self.I, self.J, self.K, self.B = int(I), int(J), int(K), int(B)
         lik = psgld_likelihood(beta, phi)
         pr = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
@@ -381,6 +383,7 @@ class PSGLD:
         opt.test_flags, opt.device, opt.graph_iters = test_flags, device, graph_iters
         opt.persistent = int(bool(persistent))
         opt.part_order = {"cyclic": PSGLD_PART_CYCLIC, "random": PSGLD_PART_RANDOM}[part_order]
+        opt.dense_min_cols = int(dense_min_cols)
         self.ctx = psgld_create(self.I, self.J, self.K, self.B, lik, pr, opt)
         self.n_heldout = 0
 
@@ -502,7 +505,7 @@ def _server_check(status, srv):
         raise PsgldError(status, msg.decode() if msg else "")
 
 
-def psgld_job_from(wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3):
+def psgld_job_from(wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3, dense_min_cols=0):
     """A psgld_job for a workload (see workloads.Workload) and the arrays it
     points to, which must stay alive until the job is submitted."""
     keep = {}
@@ -519,7 +522,7 @@ def psgld_job_from(wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshol
     j.prior = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if wl.prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
                           wl.lambda_w, wl.lambda_h, int(bool(wl.mirror)))
     j.seed, j.burn_in, j.thin = wl.seed, wl.burn_in, wl.thin
-    j.precision, j.dense_threshold = precision, dense_threshold
+    j.precision, j.dense_threshold, j.dense_min_cols = precision, dense_threshold, int(dense_min_cols)
     j.sched = psgld_eps_schedule(wl.eps_a, wl.eps_t0, wl.eps_gamma)
     j.n_iter = int(n_iter)
     if dense:
@@ -560,8 +563,8 @@ class Server:
         self.srv = out.value
         self.shapes = {}
 
-    def submit(self, wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3) -> int:
-        job, keep = psgld_job_from(wl, n_iter, dense, precision, dense_threshold)
+    def submit(self, wl, n_iter, dense=False, precision=PSGLD_FP32, dense_threshold=0.3, dense_min_cols=0) -> int:
+        job, keep = psgld_job_from(wl, n_iter, dense, precision, dense_threshold, dense_min_cols)
         jid = C.c_int64()
         _server_check(lib().psgld_server_submit(self.srv, C.byref(job), C.byref(jid)), self.srv)
         del keep

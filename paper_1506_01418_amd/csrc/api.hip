@@ -829,6 +829,7 @@ void psgld_default_options(psgld_options *opt)
     opt->graph_iters = -1;
     opt->persistent = 0;
     opt->part_order = PSGLD_PART_CYCLIC;
+    opt->dense_min_cols = 256;
 }
 
 psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgld_likelihood *lik,
@@ -859,6 +860,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (o.precision != PSGLD_FP32 && o.precision != PSGLD_BF16_DENSE) return bad("unknown precision");
     if (o.device < 0) return bad("device must be >= 0");
     if (o.part_order != PSGLD_PART_CYCLIC && o.part_order != PSGLD_PART_RANDOM) return bad("unknown part order");
+    if (o.dense_min_cols < 1) return bad("dense_min_cols must be >= 1");
 
     psgld_ctx *c = new (std::nothrow) psgld_ctx();
     if (!c) {
@@ -941,8 +943,9 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
             psgld_status s = check_values(c, 1, V + m);
             if (s) return c->fail(s, c->err + " (cell " + std::to_string(i) + ", " + std::to_string(j) + ")");
         }
-    // Dense blocks need contiguous pieces, at most kDenseMaxRows rows, rank at
-    // most kDenseMaxK, and a training density above the threshold.
+    // Dense blocks need contiguous pieces, at most kDenseMaxRows rows, at
+    // least options.dense_min_cols columns, rank at most kDenseMaxK, and a
+    // training density above the threshold.
     const bool contiguous = std::is_sorted(c->row_piece.begin(), c->row_piece.end()) &&
                             std::is_sorted(c->col_piece.begin(), c->col_piece.end());
     std::vector<int64_t> r0(B + 1, 0), c0(B + 1, 0);
@@ -963,7 +966,8 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
                     for (int64_t j = c0[cc]; j < c0[cc + 1]; ++j) cnt += mask ? (mask[i * J + j] != 0) : 1;
                 train[static_cast<size_t>(b) * B + cc] = cnt;
                 dense[static_cast<size_t>(b) * B + cc] =
-                    m <= kDenseMaxRows && cnt > c->opt.dense_threshold * static_cast<double>(m * nn);
+                    m <= kDenseMaxRows && nn >= c->opt.dense_min_cols &&
+                    cnt > c->opt.dense_threshold * static_cast<double>(m * nn);
             }
     }
     // coordinates of the sparse blocks

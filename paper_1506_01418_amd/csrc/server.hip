@@ -140,6 +140,7 @@ psgld_status load_job(psgld_server *srv, Job *j)
     o.thin = s.thin;
     o.precision = s.precision;
     o.dense_threshold = s.dense_threshold;
+    if (s.dense_min_cols > 0) o.dense_min_cols = s.dense_min_cols;
     o.stream = srv->stream;
     o.device = srv->opt.device;
     o.graph_iters = -1;

@@ -30,7 +30,9 @@ def step_parity(wl, steps_before=0, flags=0, sampler=None, dense=False, **overri
     """Runs the GPU chain `steps_before` iterations, hands its FP32 state to
     the oracle, then takes one more iteration on both and returns the worst
     scaled error over W and H (and the sampler)."""
-    s = sampler or pkg.PSGLD.from_workload(wl, dense=dense, test_flags=flags, **overrides)
+    kw = dict(dense_min_cols=1) if dense else {}   # keep narrow test blocks on the dense kernels
+    kw.update(overrides)
+    s = sampler or pkg.PSGLD.from_workload(wl, dense=dense, test_flags=flags, **kw)
     if steps_before:
         s.step(steps_before, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     Wg, Hg = s.factors()

@@ -39,7 +39,7 @@ def _shared(wls, dense_last=False, **kw):
     out = [first]
     for m, wl in enumerate(wls[1:]):
         dense = dense_last and m == len(wls) - 2
-        out.append(pkg.PSGLD.from_workload(wl, dense=dense, stream=first.stream(), **kw))
+        out.append(pkg.PSGLD.from_workload(wl, dense=dense, stream=first.stream(), dense_min_cols=1, **kw))
     return out
 
 
@@ -54,7 +54,7 @@ def _sched(wl):
 
 def test_batch_matches_each_context_alone():
     wls = _cases() + [dense_case(128, 300, 16, 2, 0.5, density=0.9, seed=41)]
-    alone = [pkg.PSGLD.from_workload(wl, dense=(m == len(wls) - 1), burn_in=5, thin=2)
+    alone = [pkg.PSGLD.from_workload(wl, dense=(m == len(wls) - 1), burn_in=5, thin=2, dense_min_cols=1)
              for m, wl in enumerate(wls)]
     together = _shared(wls, dense_last=True, burn_in=5, thin=2)
     plans = [[12, 7, 12, 3, 12, 9], [1, 20, 0, 5, 8, 20]]

@@ -70,7 +70,7 @@ def test_mixed_dense_and_sparse_blocks():
     """Diagonal blocks dense, the others below the threshold: each part mixes
     the dense kernels and the coordinate kernel."""
     wl = dense_case(256, 240, 16, 4, 1.0, seed=4, block_density=lambda b, c: 0.8 if b == c else 0.1)
-    s = pkg.PSGLD.from_workload(wl, dense=True)
+    s = pkg.PSGLD.from_workload(wl, dense=True, dense_min_cols=1)
     for t in range(6):
         err, _ = step_parity(wl, 0, sampler=s)
         assert err <= TOL_FP32, (t, err)
@@ -87,7 +87,7 @@ def test_tall_blocks_fall_back_to_coordinates():
 def test_dense_heldout_moments_and_loglik():
     wl = dense_case(160, 400, 16, 4, 1.0, seed=6)
     wl.burn_in, wl.thin = 4, 2
-    s = pkg.PSGLD.from_workload(wl, dense=True)
+    s = pkg.PSGLD.from_workload(wl, dense=True, dense_min_cols=1)
     s.step(16, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     ch = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
     ch.run(16)
@@ -102,7 +102,7 @@ def test_dense_heldout_moments_and_loglik():
     ref = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, Wg, Hg)
     assert s.log_likelihood() == pytest.approx(ref.loglik(), rel=1e-10)
     with pytest.raises(pkg.PsgldError):
-        t = pkg.PSGLD.from_workload(wl, dense=True)
+        t = pkg.PSGLD.from_workload(wl, dense=True, dense_min_cols=1)
         t.load_heldout(wl.row[:2], wl.col[:2])      # training cells
     s.close()
 
@@ -115,7 +115,7 @@ def test_dense_kernels_are_the_ones_running():
     outs = {}
     for thr in (0.3, 0.99):
         for prec in (pkg.PSGLD_FP32, pkg.PSGLD_BF16_DENSE):
-            s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_threshold=thr)
+            s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_threshold=thr, dense_min_cols=1)
             s.step(2, wl.eps_a, wl.eps_t0, wl.eps_gamma)
             outs[thr, prec] = s.factors()[0]
             s.close()
@@ -127,7 +127,7 @@ def test_dense_runs_are_bitwise_reproducible():
     wl = dense_case(130, 700, 64, 2, 0.5, seed=7)
     out = []
     for _ in range(2):
-        s = pkg.PSGLD.from_workload(wl, dense=True, precision=pkg.PSGLD_BF16_DENSE)
+        s = pkg.PSGLD.from_workload(wl, dense=True, precision=pkg.PSGLD_BF16_DENSE, dense_min_cols=1)
         s.step(4, wl.eps_a, wl.eps_t0, wl.eps_gamma)
         out.append(s.factors())
         s.close()

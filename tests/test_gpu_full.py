@@ -32,7 +32,7 @@ def test_sparse_ratings_full_size_step_parity():
 def test_dense_tweedie_block_shape_parity(bf16):
     wl = workloads.dense_tweedie(J=4000, name="dense_tweedie_1025x4k")
     prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
-    s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec)
+    s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_min_cols=1)
     err0, _ = step_parity(wl, 0, sampler=s)
     err1, _ = step_parity(wl, 5, sampler=s)
     s.close()

@@ -68,8 +68,10 @@ def test_graph_dense_blocks_match_single_launches(bf16):
     wl = dense_case(150, 700, 32, 4, 0.5, density=0.85, seed=21,
                     block_density=lambda b, c: 0.85 if (b + c) % 2 == 0 else 0.1)
     prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
-    eager = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, burn_in=6, graph_iters=-1)
-    graph = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, burn_in=6, graph_iters=8)
+    eager = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, burn_in=6, graph_iters=-1,
+                                  dense_min_cols=1)
+    graph = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, burn_in=6, graph_iters=8,
+                                  dense_min_cols=1)
     for n in (5, 17, 8, 2):
         eager.step(n, wl.eps_a, wl.eps_t0, wl.eps_gamma)
         graph.step(n, wl.eps_a, wl.eps_t0, wl.eps_gamma)

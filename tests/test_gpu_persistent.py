@@ -55,9 +55,11 @@ def test_persistent_batch_matches_alone():
     wls = [CASES[n]() for n in ("K5_gamma", "K16_gauss", "K50_zipf", "K8_poisson")]
     wls.append(dense_case(128, 300, 16, 2, 0.5, density=0.9, seed=79))
     dense = [False] * 4 + [True]
-    alone = [pkg.PSGLD.from_workload(wl, dense=d, burn_in=5, graph_iters=-1) for wl, d in zip(wls, dense)]
+    alone = [pkg.PSGLD.from_workload(wl, dense=d, burn_in=5, graph_iters=-1, dense_min_cols=1)
+             for wl, d in zip(wls, dense)]
     first = pkg.PSGLD.from_workload(wls[0], burn_in=5, persistent=1)
-    together = [first] + [pkg.PSGLD.from_workload(wl, dense=d, burn_in=5, persistent=1, stream=first.stream())
+    together = [first] + [pkg.PSGLD.from_workload(wl, dense=d, burn_in=5, persistent=1, stream=first.stream(),
+                                                  dense_min_cols=1)
                           for wl, d in zip(wls[1:], dense[1:])]
     scheds = [(wl.eps_a, wl.eps_t0, wl.eps_gamma) for wl in wls]
     for plan in ([12, 12, 7, 12, 12], [30, 0, 30, 5, 2]):

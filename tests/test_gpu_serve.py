@@ -46,12 +46,12 @@ def _drain(srv, max_ticks=200):
 def test_served_jobs_match_runs_alone():
     wls = _mix()
     srv = pkg.Server(hbm_budget=8 << 30, max_active=4, iters_per_tick=7)
-    ids = [srv.submit(wl, N_ITER, dense=_is_dense(wl)) for wl in wls]
+    ids = [srv.submit(wl, N_ITER, dense=_is_dense(wl), dense_min_cols=1) for wl in wls]
     _drain(srv)
     for jid, wl in zip(ids, wls):
         assert srv.info(jid)["state"] == pkg.PSGLD_JOB_DONE, srv.error(jid)
         Wm, Hm, Wv, Hv, rmse = srv.result(jid)
-        s = pkg.PSGLD.from_workload(wl, dense=_is_dense(wl))
+        s = pkg.PSGLD.from_workload(wl, dense=_is_dense(wl), dense_min_cols=1)
         s.step(N_ITER, wl.eps_a, wl.eps_t0, wl.eps_gamma)
         aWm, aHm = s.posterior_mean()
         aWv, aHv = s.posterior_var()
