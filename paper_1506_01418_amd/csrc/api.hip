@@ -1,8 +1,9 @@
 // Host runtime of libpsgld: the C ABI declared in psgld.h.
 //
 // Layout in device memory (HBM), built once on the host at load time:
-//  * W is I x Kp and H is stored transposed, J x Kp (Kp = K rounded up to a
-//    multiple of 4, padding held at zero), each twice (ping-pong): an
+//  * W is I x Kp and H is stored transposed, J x Kp (Kp = padded_rank(K):
+//    rows padded to whole cache lines, padding held at zero), each twice
+//    (ping-pong): an
 //    iteration reads one copy and writes the other, so every row and column
 //    update reads only the previous state (Eq. (8)-(9)).
 //  * Training entries are bucketed by part (part of (i,j) = (c - b) mod B
@@ -844,7 +845,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (!lik || !prior) return bad("likelihood and prior are required");
     if (I < 1 || J < 1 || I > INT32_MAX || J > INT32_MAX) return bad("I and J must be in [1, 2^31)");
     if (K < 1 || K > 256) return bad("K must be in [1, 256]");
-    if ((I + 1) * ((K + 3) / 4 * 4) >= INT32_MAX || (J + 1) * ((K + 3) / 4 * 4) >= INT32_MAX)
+    if ((I + 1) * padded_rank(K) >= INT32_MAX || (J + 1) * padded_rank(K) >= INT32_MAX)
         return bad("I * K and J * K must stay below 2^31");
     if (B < 1 || B > I || B > J) return bad("B must be in [1, min(I, J)]");
     if (!(lik->phi > 0.0) || !std::isfinite(lik->phi) || !std::isfinite(lik->beta)) return bad("phi must be > 0, beta finite");
@@ -871,7 +872,7 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     c->J = J;
     c->K = K;
     c->B = B;
-    c->Kp = (K + 3) / 4 * 4;
+    c->Kp = padded_rank(K);
     c->nq = (K + 3) / 4;
     c->lpg = sparse_threads_per_group(K);
     c->qpl = sparse_quads_per_lane(K);

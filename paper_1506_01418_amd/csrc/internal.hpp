@@ -18,6 +18,17 @@ struct Entry {
     float val;
 };
 
+// Floats per stored factor row: K padded so rows never straddle 128-byte
+// cache lines more than they must -- a power of two (at least 4) up to 32,
+// else a multiple of 32.  The padding is held at zero.
+inline int padded_rank(int K)
+{
+    if (K > 32) return (K + 31) / 32 * 32;
+    int p = 4;
+    while (p < K) p *= 2;
+    return p;
+}
+
 // Entries past the end of every entry array, so a batch of reads that
 // starts inside an item never leaves the allocation.
 constexpr int kEntryPad = 16;

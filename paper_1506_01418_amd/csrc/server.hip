@@ -49,7 +49,7 @@ struct Job {
 // of the load, held-out and stepping calls, by the sizes they are made with).
 int64_t estimate_bytes(const psgld_job &j)
 {
-    const int64_t I = j.I, J = j.J, B = j.B, Kp = (j.K + 3) / 4 * 4;
+    const int64_t I = j.I, J = j.J, B = j.B, Kp = padded_rank(j.K);
     const int64_t Q = sparse_block_threads() / sparse_threads_per_group(j.K);
     int64_t qlog = 0;
     while ((int64_t{1} << qlog) < Q) ++qlog;

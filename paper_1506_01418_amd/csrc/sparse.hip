@@ -270,7 +270,14 @@ __device__ __forceinline__ void item_update(const SparseIterArgs &a, const IterS
 #pragma unroll
     for (int m = 0; m < QPL; ++m) {
         const int q = quad_of<LPG>(lane, m);
-        if (q >= a.nq) continue;
+        if (q >= a.nq) {
+            // padding of the row: rewritten as zeros, so the row's cache
+            // lines are written whole
+            if (4 * q < a.Kp)
+                *reinterpret_cast<float4 *>(xnew + static_cast<size_t>(item) * a.Kp + 4 * q) =
+                    make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
         float z[4] = {0.f, 0.f, 0.f, 0.f};
         if (noisy) {
             const Normal4 nz = normal4(a.seed_lo, a.seed_hi, it.t, static_cast<uint32_t>(side),
