@@ -67,6 +67,10 @@ CASES = {
     "K30_gauss_mirror": lambda: workloads.random_sparse(400, 300, 20_000, 30, 5, beta=2.0,
                                                         prior="gaussian", mirror=True,
                                                         data_seed=15, chain_seed=16),
+    # general beta (no closed-form branch) with 4 lanes of one quad each
+    "K12_beta07_B5": lambda: workloads.random_sparse(500, 420, 25_000, 12, 5, beta=0.7,
+                                                     prior="exponential", mirror=True, zipf_a=1.0,
+                                                     data_seed=17, chain_seed=18),
 }
 
 
