@@ -450,6 +450,23 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
 
 int32_t dense_slot_rows(const psgld_ctx *c) { return (c->dense_max_m + 31) / 32 * 32; }
 
+// Rows of a dense block's MFMA tiles are padded to this: the k-depth of one
+// MFMA step over rows (4 for FP32 operands, 32 for BF16), rounded to 16.
+int dense_row_align(const psgld_ctx *c) { return c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16; }
+
+// Sub-tiles per work-group for a block of m rows: the four waves of a
+// work-group share a sub-tile's 16-row tiles, so a block of up to 64 (padded)
+// rows gives each wave one tile per sub-tile and takes four sub-tiles, a
+// taller one two tiles per wave and takes two -- the work-groups of the
+// tallest block, which set when the launch ends (all of them run at once),
+// then have about the work of the others.
+int dense_sub_tiles(int m, int row_align)
+{
+    const int MT = (m + row_align - 1) / row_align * row_align;
+    const int tiles_per_wave = (MT + 63) / 64;
+    return std::max(1, kDenseSubTiles / tiles_per_wave);
+}
+
 psgld_status check_values(psgld_ctx *c, int64_t n, const float *val)
 {
     for (int64_t e = 0; e < n; ++e) {
@@ -609,7 +626,7 @@ hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *cl
         d.mask = c->dmask;
         d.w_partial = c->w_partial;
         d.slot_rows = dense_slot_rows(c);
-        d.row_align = c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16;
+        d.row_align = dense_row_align(c);
         d.K = c->K;
         d.Kp = c->Kp;
         d.KS = c->KS;
@@ -991,6 +1008,7 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
     if ((s = build_layout(c, static_cast<int64_t>(row.size()), row.data(), col.data(), val.data()))) return s;
 
     // dense storage, part-major: values, mask, block table, tiles
+    const int row_align = dense_row_align(c);
     std::vector<float> dv;
     std::vector<DenseTile> tiles;
     c->dblock_of.assign(static_cast<size_t>(B) * B, -1);
@@ -1015,21 +1033,26 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
             blk.m = static_cast<int32_t>(r0[b + 1] - r0[b]);
             blk.col0 = static_cast<int32_t>(c0[cc]);
             blk.n = static_cast<int32_t>(c0[cc + 1] - c0[cc]);
+            blk.ld = (blk.n + kDenseRowAlign - 1) / kDenseRowAlign * kDenseRowAlign;
+            blk.n_sub = dense_sub_tiles(blk.m, row_align);
             blk.v_off = static_cast<int64_t>(dv.size());
             blk.first_partial = partial;
-            const int32_t wg_cols = kDenseTileCols * kDenseSubTiles;
+            const int32_t wg_cols = kDenseTileCols * blk.n_sub;
             blk.n_tiles = (blk.n + wg_cols - 1) / wg_cols;
             const int32_t idx_in_part = static_cast<int32_t>(c->dblocks_host.size() - c->dblk_off[p]);
             for (int32_t tt = 0; tt < blk.n_tiles; ++tt)
                 tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, {0, 0, 0, 0, 0}});
             partial += blk.n_tiles;
-            for (int64_t i = 0; i < blk.m; ++i)
+            for (int64_t i = 0; i < blk.m; ++i) {
                 for (int64_t j = 0; j < blk.n; ++j) {
                     const size_t m = static_cast<size_t>(blk.row0 + i) * J + blk.col0 + j;
                     const uint8_t t = mask ? (mask[m] != 0) : 1;
                     dv.push_back(t ? V[m] : 0.f);
                     c->dmask_host.push_back(t);
                 }
+                dv.resize(dv.size() + (blk.ld - blk.n), 0.f);
+                c->dmask_host.resize(c->dmask_host.size() + (blk.ld - blk.n), 0);
+            }
             c->dense_max_m = std::max(c->dense_max_m, blk.m);
             c->dblock_first_tile.push_back(static_cast<int64_t>(tiles.size()) - blk.n_tiles);
             c->dblock_of[static_cast<size_t>(b) * B + cc] = static_cast<int32_t>(c->dblocks_host.size());
@@ -1087,7 +1110,6 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     std::vector<std::vector<DenseHeld>> dh(c->dtiles_host.size());
     std::vector<uint8_t> dmask_dev;
     if (!c->dblocks_host.empty()) dmask_dev = c->dmask_host;
-    const int32_t wg_cols = kDenseTileCols * kDenseSubTiles;
     for (int64_t e = 0; e < n; ++e) {
         c->ho_part[e] = part_of(c, row[e], col[e]);
         const int32_t db = c->dblock_of.empty() ? -1
@@ -1095,11 +1117,12 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
         if (db >= 0) {
             const DenseBlock &blk = c->dblocks_host[db];
             const int32_t i = row[e] - blk.row0, j = col[e] - blk.col0;
-            const size_t cell = static_cast<size_t>(blk.v_off) + static_cast<size_t>(i) * blk.n + j;
+            const size_t cell = static_cast<size_t>(blk.v_off) + static_cast<size_t>(i) * blk.ld + j;
             if (c->dmask_host[cell] == kMaskTrain) return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
             if (dmask_dev[cell] == kMaskHeld) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
             dmask_dev[cell] = kMaskHeld;
             in_dense[e] = 1;
+            const int32_t wg_cols = kDenseTileCols * blk.n_sub;
             dh[c->dblock_first_tile[db] + j / wg_cols].push_back(DenseHeld{i, j % wg_cols, static_cast<int32_t>(e), 0});
             continue;
         }

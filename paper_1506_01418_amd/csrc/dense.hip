@@ -5,8 +5,8 @@
 //   E   = mask * (V - mu~) mu~^(beta-2) / phi
 //   G_H = W_b^T E                (K x |C_c|: complete per column)
 //   G_W = E H_c^T                (|R_b| x K: summed over the block's columns)
-// A work-group owns up to kDenseSubTiles x 64 columns of one block and all
-// of its m <= 128 rows.  The three products run on MFMA 16x16 tiles (FP32
+// A work-group owns up to kDenseSubTiles x 64 columns of one block (fewer
+// for blocks taller than 64 rows) and all of its m <= 128 rows.  The three products run on MFMA 16x16 tiles (FP32
 // operands, or BF16 operands rounded to nearest even, always FP32
 // accumulation) from LDS copies of W_b, a 64-column sub-tile of H and E,
 // with four independent accumulators per wave.  The H columns are updated
@@ -166,16 +166,59 @@ __device__ __forceinline__ void stage_store(const Stage &st, float *lds, int j0,
     }
 }
 
+// Register staging of the values and mask bytes of a sub-tile's first 64
+// rows: four float4 of values and 16 mask bytes per thread, each a 16-byte
+// aligned load (rows start on 64-byte boundaries), so a wave reads whole
+// 256-byte row pieces.  Cells past the block's rows or its padded width read
+// as missing.
+struct VStage {
+    float4 v[4];
+    uint4 mk;
+};
+
+__device__ __forceinline__ void vstage_load(VStage &st, const float *V, const uint8_t *M, int ld, int m, int cl,
+                                            int tid)
+{
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * kDenseThreads;
+        const int j = f >> 4, c = cl + 4 * (f & 15);
+        st.v[u] = (j < m && c < ld) ? load4(V + static_cast<size_t>(j) * ld + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int j = tid >> 2, c = cl + 16 * (tid & 3);
+    st.mk = (j < m && c < ld) ? *reinterpret_cast<const uint4 *>(M + static_cast<size_t>(j) * ld + c)
+                              : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Values into rows 0 .. min(64, rows) - 1 of sV (row stride `stride`; sV
+// has `rows` rows), mask bytes into sM (64 x 64, row stride 64).
+__device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int stride, int rows, uint8_t *sM,
+                                             int tid)
+{
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * kDenseThreads;
+        if ((f >> 4) >= rows) continue;
+        float *d = sV + (f >> 4) * stride + 4 * (f & 15);
+        d[0] = st.v[u].x;
+        d[1] = st.v[u].y;
+        d[2] = st.v[u].z;
+        d[3] = st.v[u].w;
+    }
+    *reinterpret_cast<uint4 *>(sM + (tid >> 2) * 64 + 16 * (tid & 3)) = st.mk;
+}
+
 // One work-group: up to kDenseSubTiles consecutive 64-column sub-tiles of
 // one block.  Wave w takes 16-row tiles w, w+4, ... of mu; the products over
 // the rank (G_H and G_W) use one 16-row k-tile per wave (K <= 64).  The next
 // sub-tile's H columns are loaded into registers while the current one is
-// computed, and each row tile's values and mask bytes are loaded before its
-// product, so no product waits on a round trip to memory it could have
-// started earlier.  G_W accumulates in registers over the sub-tiles and is
-// written once, as this work-group's partial.
+// computed, and so are the values and mask bytes of its first 64 rows (rows
+// past 64 are loaded before their row tile's product), so no product waits
+// on a round trip to memory it could have started earlier.  G_W accumulates
+// in registers over the sub-tiles and is written once, as this work-group's
+// partial.
 template <bool BF16, int LIK>
-__global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs a)
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void dense_tile_kernel(DenseIterArgs a)
 {
     extern __shared__ float lds[];
     const DenseTile tile = a.tiles[blockIdx.x];
@@ -188,7 +231,8 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
     const int se = kNT + 1;
     float *sW = lds;                   // [MT][KS+1]   W_b
     float *sH = sW + MT * sw;          // [NT][KS+1]   H columns of the sub-tile
-    float *sE = sH + kNT * sw;         // [MT][NT+1]   E
+    float *sE = sH + kNT * sw;         // [MT][NT+1]   values of the sub-tile, then E
+    uint8_t *sM = reinterpret_cast<uint8_t *>(sE + MT * se);   // [64][64] mask bytes of rows 0..63
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, h4 = lane >> 4;
     const float *Wold = a.x_old[0], *Hold = a.x_old[1];
@@ -203,6 +247,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
 
     const float *V = a.val + blk.v_off;
     const uint8_t *M = a.mask + blk.v_off;
+    const int ld = blk.ld;
+    VStage vs;
+    vstage_load(vs, V, M, ld, m, tile.col, tid);
     const int kt = wave;                          // this wave's k-tile in G_H and G_W
     const bool has_kt = kt * 16 < KS;
     const int n_it = MT / 16;                     // 16-row tiles of the block
@@ -210,33 +257,48 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
 #pragma unroll
     for (int t = 0; t < kDenseMaxRows / 16; ++t) gw[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    for (int sub = 0; sub < kDenseSubTiles; ++sub) {
+    for (int sub = 0; sub < blk.n_sub; ++sub) {
         const int cl = tile.col + sub * kNT;      // first column of the sub-tile, in the block
         if (cl >= blk.n) break;
         const int ncol = min(kNT, blk.n - cl);
         const int col0 = blk.col0 + cl;
-        __syncthreads();                          // previous sub-tile done with sH, sE
+        __syncthreads();                          // previous sub-tile done with sH, sE, sM
         stage_store(hs, sH, 0, kNT, sw, KS, tid);
-        if (sub + 1 < kDenseSubTiles && cl + kNT < blk.n)
+        vstage_store(vs, sE, se, MT, sM, tid);
+        if (sub + 1 < blk.n_sub && cl + kNT < blk.n) {
             stage_load(hs, Hold, col0 + kNT, min(kNT, blk.n - cl - kNT), Kp, tid);
+            vstage_load(vs, V, M, ld, m, cl + kNT, tid);
+        }
         __syncthreads();
 
-        // mu = W_b H^T (MT x 64) and E, one 16-row tile at a time; the tile's
-        // values and mask bytes (clamped into the block, masked after) are
-        // requested before its product
+        // mu = W_b H^T (MT x 64) and E, one 16-row tile at a time; values and
+        // mask bytes of rows 0..63 come from LDS, those of later rows
+        // (clamped into the block, masked after) are requested before the
+        // tile's product
         for (int it = wave; it < n_it; it += kDenseThreads / 64) {
             float vv[4][4];
             uint32_t mm[4][4];
+            if (it < 4) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = min(it * 16 + 4 * h4 + r, m - 1);
-                    const int j = min(t * 16 + c16, ncol - 1);
-                    const size_t cell = static_cast<size_t>(i) * blk.n + cl + j;
-                    vv[t][r] = V[cell];
-                    mm[t][r] = M[cell];
-                }
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = it * 16 + 4 * h4 + r, j = t * 16 + c16;
+                        vv[t][r] = sE[i * se + j];
+                        mm[t][r] = sM[i * 64 + j];
+                    }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = min(it * 16 + 4 * h4 + r, m - 1);
+                        const int j = min(t * 16 + c16, ncol - 1);
+                        const size_t cell = static_cast<size_t>(i) * ld + cl + j;
+                        vv[t][r] = V[cell];
+                        mm[t][r] = M[cell];
+                    }
+            }
             v4f acc[4] = {};
             mma16<BF16, 4>(acc, 4, KS, lane, [&](int r, int k) { return sW[(it * 16 + r) * sw + k]; },
                            [&](int t, int k, int c) { return sH[(t * 16 + c) * sw + k]; });
@@ -312,7 +374,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile_kernel(DenseIterArgs
 
 // W rows of the part's dense blocks: sum the tiles' partials in tile order,
 // then the Langevin step.  One thread per (row, quad).
-__global__ void dense_w_update_kernel(DenseIterArgs a)
+__global__ __launch_bounds__(128) void dense_w_update_kernel(DenseIterArgs a)
 {
     const int b = blockIdx.y;
     const DenseBlock blk = a.blocks[b];
@@ -321,22 +383,25 @@ __global__ void dense_w_update_kernel(DenseIterArgs a)
     if (w >= blk.m * nq) return;
     const int i = w / nq, k0 = 4 * (w % nq);
     const IterScalars it = iter_scalars(a.clk);
-    // partials loaded eight at a time, added in partial order
+    // partials loaded 32 at a time (one round trip for most blocks), added in
+    // partial order
+    constexpr int kBatchP = 32;
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
     const float *base = a.w_partial + (static_cast<size_t>(blk.first_partial) * a.slot_rows + i) * a.Kp + k0;
     const size_t stride = static_cast<size_t>(a.slot_rows) * a.Kp;
-    for (int t0 = 0; t0 < blk.n_tiles; t0 += 8) {
-        float4 p[8];
+    for (int t0 = 0; t0 < blk.n_tiles; t0 += kBatchP) {
+        float4 p[kBatchP];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (t0 + u < blk.n_tiles) p[u] = *reinterpret_cast<const float4 *>(base + (t0 + u) * stride);
+        for (int u = 0; u < kBatchP; ++u)   // past the last partial: the last one again, not added
+            p[u] = *reinterpret_cast<const float4 *>(base + min(t0 + u, blk.n_tiles - 1) * stride);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (t0 + u >= blk.n_tiles) break;
-            g.x += p[u].x;
-            g.y += p[u].y;
-            g.z += p[u].z;
-            g.w += p[u].w;
+        for (int u = 0; u < kBatchP; ++u) {
+            if (t0 + u < blk.n_tiles) {
+                g.x += p[u].x;
+                g.y += p[u].y;
+                g.z += p[u].z;
+                g.w += p[u].w;
+            }
         }
     }
     const float *x = a.x_old[0] + static_cast<size_t>(blk.row0 + i) * a.Kp + k0;
@@ -365,7 +430,8 @@ size_t dense_lds_bytes(int max_m, int KS)
 {
     const int MT = (max_m + 31) / 32 * 32;   // at least the padded height of any block
     return sizeof(float) * (static_cast<size_t>(MT) * (KS + 1) + static_cast<size_t>(kNT) * (KS + 1) +
-                            static_cast<size_t>(MT) * (kNT + 1));
+                            static_cast<size_t>(MT) * (kNT + 1)) +
+           64 * kNT;                             // mask bytes of rows 0..63
 }
 
 hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max_m, hipStream_t stream)

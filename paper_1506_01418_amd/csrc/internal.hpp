@@ -222,15 +222,22 @@ constexpr int kDenseMaxRows = 128;   // dense blocks have at most this many rows
 constexpr int kDenseMaxK = 64;       // and rank at most this
 
 // A dense block of a part: rows [row0, row0 + m), columns [col0, col0 + n);
-// its values and training mask are stored row-major (row stride n) at v_off;
-// its tiles' W partials occupy slots first_partial .. + n_tiles.
+// its values and mask bytes are stored row-major at v_off with row stride
+// ld = n rounded up to kDenseRowAlign cells (the padding cells are missing:
+// value 0, mask 0), so every row starts on a 64-byte boundary of the values
+// and a 16-byte boundary of the mask.  Each of its n_tiles work-groups
+// takes n_sub consecutive 64-column sub-tiles (fewer for taller blocks, so
+// every work-group has about the same work); their W partials occupy slots
+// first_partial .. + n_tiles.
+constexpr int kDenseRowAlign = 16;
 struct DenseBlock {
     int32_t row0, m, col0, n;
     int64_t v_off;
     int32_t first_partial, n_tiles;
+    int32_t ld, n_sub;
 };
 
-// One work-group's share of a block: columns [col, col + kDenseSubTiles * 64)
+// One work-group's share of a block: columns [col, col + n_sub * 64)
 // of part block `block`; its W partial goes to slot `partial`; the held-out
 // cells of its sub-tile s are heldout[ho[s] .. ho[s + 1]).
 struct DenseTile {

@@ -92,14 +92,15 @@ __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
     double acc = 0.0;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * kLLThreads + threadIdx.x; e < cells;
          e += static_cast<int64_t>(per_block) * kLLThreads) {
-        if (mask[blk.v_off + e] != kMaskTrain) continue;
         const int i = static_cast<int>(e / blk.n), j = static_cast<int>(e % blk.n);
+        const int64_t cell = blk.v_off + static_cast<int64_t>(i) * blk.ld + j;
+        if (mask[cell] != kMaskTrain) continue;
         const float *w = W + static_cast<size_t>(blk.row0 + i) * Kp;
         const float *h = Hs + static_cast<size_t>(blk.col0 + j) * Kp;
         double mu = 0.0;
         for (int k = 0; k < K; ++k) mu += static_cast<double>(w[k]) * static_cast<double>(h[k]);
         if (beta < 2.0 && mu < mu_floor) mu = mu_floor;
-        acc -= dbeta(static_cast<double>(val[blk.v_off + e]), mu, beta) / phi;
+        acc -= dbeta(static_cast<double>(val[cell]), mu, beta) / phi;
     }
     red[threadIdx.x] = acc;
     __syncthreads();

@@ -74,9 +74,9 @@ int64_t estimate_bytes(const psgld_job &j)
     b += 8 * cap;                                                  // step-size table
     b += 4 * (B * I + 1) + 32 * j.n_heldout;                       // held-out offsets, cells, sums
     if (!j.row) {
-        b += 5 * I * J;                                            // dense values and mask
-        b += (J / 256 + B + 1) * int64_t{kDenseMaxRows} * Kp * 4;  // W partials
-        b += (B * B + 1) * 64 + (J / 256 + B + 1) * B * 32;        // block and tile lists
+        b += 5 * (I * J + (kDenseRowAlign - 1) * I * B);           // dense values and mask, rows padded
+        b += (J / 128 + B + 1) * int64_t{kDenseMaxRows} * Kp * 4;  // W partials
+        b += (B * B + 1) * 64 + (J / 128 + B + 1) * B * 32;        // block and tile lists
     }
     return b + (1 << 20);                                          // small buffers
 }
