@@ -93,6 +93,7 @@ struct psgld_ctx {
     std::vector<float> ho_val;
     bool ho_has_val = false;
     std::vector<int32_t> ho_part;
+    std::vector<int32_t> ho_slot;           // caller's held-out index -> position of its FP64 sum
     std::vector<int64_t> part_visits;
 
     // dense blocks (psgld_load_dense)
@@ -1173,6 +1174,20 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
                 return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
         }
     }
+    // the FP64 sums are kept in the order the kernels visit the cells --
+    // coordinate cells by (part, row, column), then dense cells by tile -- so
+    // the sums of one part are one contiguous range; ho_slot maps the
+    // caller's order to it
+    c->ho_slot.assign(static_cast<size_t>(n), -1);
+    for (size_t m = 0; m < he.size(); ++m) {
+        c->ho_slot[he[m].slot] = static_cast<int32_t>(m);
+        he[m].slot = static_cast<int32_t>(m);
+    }
+    for (size_t m = 0; m < dflat.size(); ++m) {
+        const int32_t slot = static_cast<int32_t>(he.size() + m);
+        c->ho_slot[dflat[m].slot] = slot;
+        dflat[m].slot = slot;
+    }
     if ((s = upload(c, &c->ho_ptr, pre))) return s;
     if ((s = upload(c, &c->ho_ent, he))) return s;
     if ((s = upload(c, &c->dheld, dflat))) return s;
@@ -1504,7 +1519,7 @@ psgld_status psgld_heldout_predictions(psgld_ctx *c, double *pred)
     if (c->n_ho) HIPTRY(c, hipMemcpy(sums.data(), c->ho_sum, sums.size() * sizeof(double), hipMemcpyDeviceToHost));
     for (int64_t e = 0; e < c->n_ho; ++e) {
         const int64_t v = c->part_visits[c->ho_part[e]];
-        pred[e] = v > 0 ? sums[e] / static_cast<double>(v) : NAN;
+        pred[e] = v > 0 ? sums[c->ho_slot[e]] / static_cast<double>(v) : NAN;
     }
     return PSGLD_OK;
 }
@@ -1599,7 +1614,12 @@ psgld_status psgld_get_state(psgld_ctx *c, void *buf, size_t *size)
         HIPTRY(c, hipMemcpy(p, c->sum2[side], n * sizeof(double), hipMemcpyDeviceToHost));
         p += n * sizeof(double);
     }
-    if (c->n_ho) HIPTRY(c, hipMemcpy(p, c->ho_sum, c->n_ho * sizeof(double), hipMemcpyDeviceToHost));
+    if (c->n_ho) {
+        // saved in the caller's order of the held-out cells
+        std::vector<double> sums(static_cast<size_t>(c->n_ho));
+        HIPTRY(c, hipMemcpy(sums.data(), c->ho_sum, sums.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < c->n_ho; ++e) std::memcpy(p + e * sizeof(double), &sums[c->ho_slot[e]], sizeof(double));
+    }
     p += static_cast<size_t>(c->n_ho) * sizeof(double);
     std::memcpy(p, c->part_visits.data(), static_cast<size_t>(c->B) * sizeof(int64_t));
     *size = need;
@@ -1635,7 +1655,11 @@ psgld_status psgld_set_state(psgld_ctx *c, const void *buf, size_t size)
         HIPTRY(c, hipMemcpy(c->sum2[side], p, n * sizeof(double), hipMemcpyHostToDevice));
         p += n * sizeof(double);
     }
-    if (c->n_ho) HIPTRY(c, hipMemcpy(c->ho_sum, p, c->n_ho * sizeof(double), hipMemcpyHostToDevice));
+    if (c->n_ho) {
+        std::vector<double> sums(static_cast<size_t>(c->n_ho));
+        for (int64_t e = 0; e < c->n_ho; ++e) std::memcpy(&sums[c->ho_slot[e]], p + e * sizeof(double), sizeof(double));
+        HIPTRY(c, hipMemcpy(c->ho_sum, sums.data(), sums.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     p += static_cast<size_t>(c->n_ho) * sizeof(double);
     std::memcpy(c->part_visits.data(), p, static_cast<size_t>(c->B) * sizeof(int64_t));
     c->t = hdr[6];
