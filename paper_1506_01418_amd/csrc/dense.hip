@@ -24,7 +24,7 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kDenseThreads = 256;   // 4 waves
+constexpr int kDenseThreads = 512;   // 8 waves: two per 16-row tile, k-tile or column half
 constexpr int kNT = kDenseTileCols;
 
 // D_t(16x16) += A(16 x kd) B_t(kd x 16) for t < nb (at most NACC), all with
@@ -167,27 +167,28 @@ __device__ __forceinline__ void stage_store(const Stage &st, float *lds, int j0,
 }
 
 // Register staging of the values and mask bytes of a sub-tile's first 64
-// rows: four float4 of values and 16 mask bytes per thread, each a 16-byte
-// aligned load (rows start on 64-byte boundaries), so a wave reads whole
-// 256-byte row pieces.  Cells past the block's rows or its padded width read
-// as missing.
+// rows: kVQ float4 of values and 8 mask bytes per thread, aligned loads
+// (rows start on 64-byte boundaries), so a wave reads whole 256-byte row
+// pieces.  Cells past the block's rows or its padded width read as missing.
+constexpr int kVQ = 64 * 64 / 4 / kDenseThreads;
+static_assert(64 * 64 == 8 * kDenseThreads, "one 8-byte piece of the mask per thread");
 struct VStage {
-    float4 v[4];
-    uint4 mk;
+    float4 v[kVQ];
+    uint2 mk;
 };
 
 __device__ __forceinline__ void vstage_load(VStage &st, const float *V, const uint8_t *M, int ld, int m, int cl,
                                             int tid)
 {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kVQ; ++u) {
         const int f = tid + u * kDenseThreads;
         const int j = f >> 4, c = cl + 4 * (f & 15);
         st.v[u] = (j < m && c < ld) ? load4(V + static_cast<size_t>(j) * ld + c) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    const int j = tid >> 2, c = cl + 16 * (tid & 3);
-    st.mk = (j < m && c < ld) ? *reinterpret_cast<const uint4 *>(M + static_cast<size_t>(j) * ld + c)
-                              : make_uint4(0u, 0u, 0u, 0u);
+    const int j = tid >> 3, c = cl + 8 * (tid & 7);
+    st.mk = (j < m && c < ld) ? *reinterpret_cast<const uint2 *>(M + static_cast<size_t>(j) * ld + c)
+                              : make_uint2(0u, 0u);
 }
 
 // Values into rows 0 .. min(64, rows) - 1 of sV (row stride `stride`; sV
@@ -196,7 +197,7 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
                                              int tid)
 {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kVQ; ++u) {
         const int f = tid + u * kDenseThreads;
         if ((f >> 4) >= rows) continue;
         float *d = sV + (f >> 4) * stride + 4 * (f & 15);
@@ -205,12 +206,14 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
         d[2] = st.v[u].z;
         d[3] = st.v[u].w;
     }
-    *reinterpret_cast<uint4 *>(sM + (tid >> 2) * 64 + 16 * (tid & 3)) = st.mk;
+    *reinterpret_cast<uint2 *>(sM + (tid >> 3) * 64 + 8 * (tid & 7)) = st.mk;
 }
 
 // One work-group: up to kDenseSubTiles consecutive 64-column sub-tiles of
-// one block.  Wave w takes 16-row tiles w, w+4, ... of mu; the products over
-// the rank (G_H and G_W) use one 16-row k-tile per wave (K <= 64).  The next
+// one block.  Wave w = 4 ch + wq (ch = 0, 1) takes the 16-row tiles wq,
+// wq + 4, ... of mu over column half ch of the sub-tile; in G_H it takes
+// k-tile wq over column half ch, in G_W k-tile wq over the 16-row tiles ch,
+// ch + 2, ... (K <= 64).  The next
 // sub-tile's H columns are loaded into registers while the current one is
 // computed, and so are the values and mask bytes of its first 64 rows (rows
 // past 64 are loaded before their row tile's product), so no product waits
@@ -218,7 +221,7 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
 // in registers over the sub-tiles and is written once, as this work-group's
 // partial.
 template <bool BF16, int LIK>
-__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void dense_tile_kernel(DenseIterArgs a)
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void dense_tile_kernel(DenseIterArgs a)
 {
     extern __shared__ float lds[];
     const DenseTile tile = a.tiles[blockIdx.x];
@@ -235,6 +238,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
     uint8_t *sM = reinterpret_cast<uint8_t *>(sE + MT * se);   // [64][64] mask bytes of rows 0..63
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, h4 = lane >> 4;
+    const int wq = wave & 3, ch = wave >> 2;
     const float *Wold = a.x_old[0], *Hold = a.x_old[1];
 
     // W_b (two 64-row pieces) and the first sub-tile's H columns, all in flight together
@@ -248,14 +252,20 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
     const float *V = a.val + blk.v_off;
     const uint8_t *M = a.mask + blk.v_off;
     const int ld = blk.ld;
+    // FP32 operands: values and mask bytes of rows 0..63 prefetched one
+    // sub-tile ahead; BF16 operands need those registers for the operand
+    // conversions, and read the values in place before each product
+    constexpr bool kStageV = !BF16;
     VStage vs;
-    vstage_load(vs, V, M, ld, m, tile.col, tid);
-    const int kt = wave;                          // this wave's k-tile in G_H and G_W
+    if constexpr (kStageV) vstage_load(vs, V, M, ld, m, tile.col, tid);
+    const int kt = wq;                            // this wave's k-tile in G_H and G_W
     const bool has_kt = kt * 16 < KS;
     const int n_it = MT / 16;                     // 16-row tiles of the block
-    v4f gw[kDenseMaxRows / 16];
+    constexpr int kGW = kDenseMaxRows / 32;       // G_W row tiles per wave: ch, ch + 2, ...
+    const int n_gw = (n_it - ch + 1) / 2;
+    v4f gw[kGW];
 #pragma unroll
-    for (int t = 0; t < kDenseMaxRows / 16; ++t) gw[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kGW; ++t) gw[t] = v4f{0.f, 0.f, 0.f, 0.f};
 
     for (int sub = 0; sub < blk.n_sub; ++sub) {
         const int cl = tile.col + sub * kNT;      // first column of the sub-tile, in the block
@@ -264,10 +274,10 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
         const int col0 = blk.col0 + cl;
         __syncthreads();                          // previous sub-tile done with sH, sE, sM
         stage_store(hs, sH, 0, kNT, sw, KS, tid);
-        vstage_store(vs, sE, se, MT, sM, tid);
+        if constexpr (kStageV) vstage_store(vs, sE, se, MT, sM, tid);
         if (sub + 1 < blk.n_sub && cl + kNT < blk.n) {
             stage_load(hs, Hold, col0 + kNT, min(kNT, blk.n - cl - kNT), Kp, tid);
-            vstage_load(vs, V, M, ld, m, cl + kNT, tid);
+            if constexpr (kStageV) vstage_load(vs, V, M, ld, m, cl + kNT, tid);
         }
         __syncthreads();
 
@@ -275,36 +285,36 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
         // mask bytes of rows 0..63 come from LDS, those of later rows
         // (clamped into the block, masked after) are requested before the
         // tile's product
-        for (int it = wave; it < n_it; it += kDenseThreads / 64) {
-            float vv[4][4];
-            uint32_t mm[4][4];
-            if (it < 4) {
+        for (int it = wq; it < n_it; it += 4) {
+            float vv[2][4];
+            uint32_t mm[2][4];
+            if (kStageV && it < 4) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 2; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int i = it * 16 + 4 * h4 + r, j = t * 16 + c16;
+                        const int i = it * 16 + 4 * h4 + r, j = (2 * ch + t) * 16 + c16;
                         vv[t][r] = sE[i * se + j];
                         mm[t][r] = sM[i * 64 + j];
                     }
             } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 2; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int i = min(it * 16 + 4 * h4 + r, m - 1);
-                        const int j = min(t * 16 + c16, ncol - 1);
+                        const int j = min((2 * ch + t) * 16 + c16, ncol - 1);
                         const size_t cell = static_cast<size_t>(i) * ld + cl + j;
                         vv[t][r] = V[cell];
                         mm[t][r] = M[cell];
                     }
             }
-            v4f acc[4] = {};
-            mma16<BF16, 4>(acc, 4, KS, lane, [&](int r, int k) { return sW[(it * 16 + r) * sw + k]; },
-                           [&](int t, int k, int c) { return sH[(t * 16 + c) * sw + k]; });
+            v4f acc[2] = {};
+            mma16<BF16, 2>(acc, 2, KS, lane, [&](int r, int k) { return sW[(it * 16 + r) * sw + k]; },
+                           [&](int t, int k, int c) { return sH[((2 * ch + t) * 16 + c) * sw + k]; });
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int j = t * 16 + c16;
+            for (int t = 0; t < 2; ++t) {
+                const int j = (2 * ch + t) * 16 + c16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = it * 16 + 4 * h4 + r;
@@ -333,15 +343,15 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
         }
 
         if (has_kt) {
-            // G_H = W_b^T E (k-tile kt x 64 columns): update the sub-tile's H columns
-            v4f acc[4] = {};
-            mma16<BF16, 4>(acc, 4, MT, lane, [&](int r, int i) { return sW[i * sw + kt * 16 + r]; },
-                           [&](int t, int i, int c) { return sE[i * se + t * 16 + c]; });
+            // G_H = W_b^T E (k-tile kt x column half ch): update those H columns
+            v4f acc[2] = {};
+            mma16<BF16, 2>(acc, 2, MT, lane, [&](int r, int i) { return sW[i * sw + kt * 16 + r]; },
+                           [&](int t, int i, int c) { return sE[i * se + (2 * ch + t) * 16 + c]; });
             const int k0 = kt * 16 + 4 * h4;      // four consecutive k: one Philox quad
             if (k0 < Kp) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int j = t * 16 + c16;
+                for (int t = 0; t < 2; ++t) {
+                    const int j = (2 * ch + t) * 16 + c16;
                     if (j >= ncol) continue;
                     const float g[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
                     const float xo[4] = {sH[j * sw + k0], sH[j * sw + k0 + 1], sH[j * sw + k0 + 2],
@@ -349,10 +359,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
                     dense_langevin(a, itr, 1, col0 + j, k0, xo, g);
                 }
             }
-            // G_W^T += H^T E^T (k-tile kt x MT rows)
-            mma16<BF16, kDenseMaxRows / 16>(gw, n_it, kNT, lane,
-                                            [&](int r, int j) { return sH[j * sw + kt * 16 + r]; },
-                                            [&](int t, int j, int c) { return sE[(t * 16 + c) * se + j]; });
+            // G_W^T += H^T E^T (k-tile kt x row tiles ch, ch + 2, ...)
+            mma16<BF16, kGW>(gw, n_gw, kNT, lane, [&](int r, int j) { return sH[j * sw + kt * 16 + r]; },
+                             [&](int t, int j, int c) { return sE[((ch + 2 * t) * 16 + c) * se + j]; });
         }
     }
 
@@ -362,9 +371,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(2
         if (k0 < Kp) {
             float *part = a.w_partial + static_cast<size_t>(tile.partial) * a.slot_rows * Kp;
 #pragma unroll
-            for (int t = 0; t < kDenseMaxRows / 16; ++t) {
-                if (t >= n_it) break;
-                const int i = t * 16 + c16;
+            for (int t = 0; t < kGW; ++t) {
+                if (t >= n_gw) break;
+                const int i = (ch + 2 * t) * 16 + c16;
                 *reinterpret_cast<float4 *>(part + static_cast<size_t>(i) * Kp + k0) =
                     make_float4(gw[t][0], gw[t][1], gw[t][2], gw[t][3]);
             }
