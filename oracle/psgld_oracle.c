@@ -16,7 +16,7 @@
  *     priors exponential (rate lambda, on |x|) or Gaussian (precision lambda).
  *   - Blocks and parts, Section 3 Definitions 1-2: contiguous partitions of
  *     [I] and [J] into B pieces; part p = { (b, (b+p) mod B) : b = 0..B-1 },
- *     chosen in cyclic order p = t mod B (Section 4.2.1 "cyclic order").
+ *     chosen in cyclic order p = t mod B (Section 4.2.1).
  *   - Update, Eq. (8)-(9): for every block of the part,
  *       x <- x + eps_t * ( N/|Pi_t| * sum_{(i,j) in block} d/dx log p(v_ij|.)
  *                          + d/dx log p(x) ) + N(0, 2 eps_t)
