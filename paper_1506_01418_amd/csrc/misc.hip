@@ -36,10 +36,17 @@ __global__ void normals_kernel(int64_t n, uint32_t seed_lo, uint32_t seed_hi, co
     }
 }
 
-// beta-divergence d_beta(v||mu), with the KL and IS limits at beta = 1, 0.
+// beta-divergence d_beta(v||mu), with the KL and IS limits at beta = 1, 0,
+// and the general formula in closed form at beta = 2 (half the squared
+// difference) and beta = 1/2 (-4 sqrt(v) + 2 v / sqrt(mu) + 2 sqrt(mu)).
 __device__ double dbeta(double v, double mu, double beta)
 {
+    if (beta == 2.0) return 0.5 * (v - mu) * (v - mu);
     if (beta == 1.0) return (v > 0.0 ? v * log(v / mu) : 0.0) - v + mu;
+    if (beta == 0.5) {
+        const double r = sqrt(mu);
+        return -4.0 * sqrt(v) + 2.0 * v / r + 2.0 * r;
+    }
     if (beta == 0.0) return v / mu - log(v / mu) - 1.0;
     return pow(v, beta) / (beta * (beta - 1.0)) - v * pow(mu, beta - 1.0) / (beta - 1.0) +
            pow(mu, beta) / beta;
@@ -65,10 +72,16 @@ __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
     double acc = 0.0;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * kLLThreads + threadIdx.x; e < n;
          e += static_cast<int64_t>(gridDim.x) * kLLThreads) {
-        const float *w = W + static_cast<size_t>(row_of_entry[e]) * Kp;
-        const float *h = Hs + ent[e].off;
+        const float4 *w = reinterpret_cast<const float4 *>(W + static_cast<size_t>(row_of_entry[e]) * Kp);
+        const float4 *h = reinterpret_cast<const float4 *>(Hs + ent[e].off);
         double mu = 0.0;
-        for (int k = 0; k < K; ++k) mu += static_cast<double>(w[k]) * static_cast<double>(h[k]);
+        for (int q = 0; 4 * q < K; ++q) {      // rows hold Kp >= K floats, zero past K
+            const float4 a = w[q], b = h[q];
+            mu += static_cast<double>(a.x) * static_cast<double>(b.x);
+            mu += static_cast<double>(a.y) * static_cast<double>(b.y);
+            mu += static_cast<double>(a.z) * static_cast<double>(b.z);
+            mu += static_cast<double>(a.w) * static_cast<double>(b.w);
+        }
         if (beta < 2.0 && mu < mu_floor) mu = mu_floor;
         acc -= dbeta(static_cast<double>(ent[e].val), mu, beta) / phi;
     }
@@ -95,10 +108,16 @@ __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
         const int i = static_cast<int>(e / blk.n), j = static_cast<int>(e % blk.n);
         const int64_t cell = blk.v_off + static_cast<int64_t>(i) * blk.ld + j;
         if (mask[cell] != kMaskTrain) continue;
-        const float *w = W + static_cast<size_t>(blk.row0 + i) * Kp;
-        const float *h = Hs + static_cast<size_t>(blk.col0 + j) * Kp;
+        const float4 *w = reinterpret_cast<const float4 *>(W + static_cast<size_t>(blk.row0 + i) * Kp);
+        const float4 *h = reinterpret_cast<const float4 *>(Hs + static_cast<size_t>(blk.col0 + j) * Kp);
         double mu = 0.0;
-        for (int k = 0; k < K; ++k) mu += static_cast<double>(w[k]) * static_cast<double>(h[k]);
+        for (int q = 0; 4 * q < K; ++q) {      // rows hold Kp >= K floats, zero past K
+            const float4 a = w[q], b = h[q];
+            mu += static_cast<double>(a.x) * static_cast<double>(b.x);
+            mu += static_cast<double>(a.y) * static_cast<double>(b.y);
+            mu += static_cast<double>(a.z) * static_cast<double>(b.z);
+            mu += static_cast<double>(a.w) * static_cast<double>(b.w);
+        }
         if (beta < 2.0 && mu < mu_floor) mu = mu_floor;
         acc -= dbeta(static_cast<double>(val[cell]), mu, beta) / phi;
     }
