@@ -51,14 +51,19 @@ def test_dense_poisson_256_parity(bf16, steps_before):
 
 
 @pytest.mark.parametrize("bf16", [False, True])
-@pytest.mark.parametrize("case", ["cpois_K64_m65", "gauss_K20_ragged", "gamma_K8_B5", "unequal_heights"])
+@pytest.mark.parametrize("case", ["cpois_K64_m65", "gauss_K20_ragged", "gamma_K8_B5", "unequal_heights",
+                                  "kl_K48_m128"])
 def test_dense_parity_shapes(case, bf16):
     wl = {"cpois_K64_m65": lambda: dense_case(130, 1000, 64, 2, 0.5, seed=1),
           "gauss_K20_ragged": lambda: dense_case(201, 333, 20, 3, 2.0, seed=2, prior="gaussian",
                                                  mirror=False),
           "gamma_K8_B5": lambda: dense_case(150, 170, 8, 5, 0.0, seed=3),
           # pieces of 33, 32 and 32 rows: blocks of one part pad to different heights
-          "unequal_heights": lambda: dense_case(97, 400, 16, 3, 1.0, seed=9)}[case]()
+          "unequal_heights": lambda: dense_case(97, 400, 16, 3, 1.0, seed=9),
+          # the tallest blocks (128 rows: four G_W row tiles per wave, two
+          # sub-tiles per work-group) and K = 48 (with FP32 operands one
+          # wave in four has no k-tile)
+          "kl_K48_m128": lambda: dense_case(256, 600, 48, 2, 1.0, seed=11)}[case]()
     prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
     for steps in (0, 4):
         err, s = step_parity(wl, steps, dense=True, precision=prec)
