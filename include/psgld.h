@@ -111,8 +111,8 @@ typedef struct {
     int32_t device;           /* HIP device ordinal */
     int32_t graph_iters;      /* iterations per captured HIP graph in psgld_step:
                                  < 0 = never capture, one launch sequence per
-                                 iteration (the default: on MI355X it measured
-                                 faster than graph replay); 0 = one cycle of B
+                                 iteration (the default: on MI355X graph replay
+                                 measured no faster); 0 = one cycle of B
                                  parts repeated to at least 32 iterations;
                                  > 0 = that many iterations */
     int32_t persistent;       /* 1: contexts without dense blocks run their
