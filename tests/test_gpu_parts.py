@@ -26,6 +26,23 @@ def test_random_order_step_parity(steps_before):
     assert err <= TOL_FP32, err
 
 
+@pytest.mark.parametrize("bf16", [False, True])
+def test_random_order_dense_and_mixed_blocks(bf16):
+    """Random order over parts that mix dense blocks (MFMA kernels) and
+    coordinate blocks: the drawn part decides which blocks and which scale
+    each iteration uses on both paths."""
+    from test_gpu_dense import dense_case
+    # row pieces 0 and 2 dense, 1 and 3 sparse: every part has both kinds
+    wl = dense_case(150, 700, 32, 4, 0.5, density=0.85, seed=95,
+                    block_density=lambda b, c: 0.85 if b % 2 == 0 else 0.1)
+    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    from parity import TOL_BF16
+    for steps in (0, 6):
+        err, s = step_parity(wl, steps, dense=True, precision=prec, part_order="random")
+        s.close()
+        assert err <= (TOL_BF16 if bf16 else TOL_FP32), (steps, err)
+
+
 def test_random_order_launch_modes_agree():
     wl = _zipf()
     kw = dict(burn_in=5, thin=2, part_order="random")
