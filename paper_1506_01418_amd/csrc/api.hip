@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "runtime.hpp"
 #include "noise.hpp"
 #include "psgld.h"
 
@@ -153,6 +154,15 @@ struct psgld_ctx {
             return (ctx)->fail(PSGLD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Makes `dev` the calling thread's device; hipSetDevice only when it is not
+// already (the call costs tens of microseconds even when nothing changes).
+hipError_t psgld::use_device(int dev)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur == dev) return hipSuccess;
+    return hipSetDevice(dev);
+}
+
 namespace {
 
 template <typename T>
@@ -199,7 +209,7 @@ psgld_status ensure_device(psgld_ctx *c)
         (void)hipGetLastError();
         return c->fail(PSGLD_E_DEVICE, "no HIP device " + std::to_string(c->opt.device));
     }
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     if (!is_gfx950(c->opt.device)) return c->fail(PSGLD_E_DEVICE, "device is not gfx950 (MI355X)");
     if (c->opt.stream) {
         c->stream = static_cast<hipStream_t>(c->opt.stream);
@@ -207,7 +217,6 @@ psgld_status ensure_device(psgld_ctx *c)
         HIPTRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
-    HIPTRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     psgld_status s = dev_alloc(c, &c->nonfinite, 1);
     if (s) return s;
     if ((s = dev_alloc(c, &c->clock, 1))) return s;
@@ -493,7 +502,7 @@ psgld_status check_coords(psgld_ctx *c, int64_t n, const int32_t *row, const int
 psgld_status sync_and_check(psgld_ctx *c)
 {
     if (!c->device_ready) return PSGLD_OK;
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     int32_t flag = INT_MAX;
     HIPTRY(c, hipMemcpy(&flag, c->nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
@@ -684,6 +693,9 @@ psgld_status get_graph(psgld_ctx *c, int32_t r, int cur, int64_t L, hipGraphExec
         *out = it->second;
         return PSGLD_OK;
     }
+    // the capture stream is created on first capture: creating a stream costs
+    // about a millisecond, which contexts that never capture should not pay
+    if (!c->cap_stream) HIPTRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIPTRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int64_t k = 0; k < L && e == hipSuccess; ++k)
@@ -1221,7 +1233,7 @@ psgld_status psgld_set_factors(psgld_ctx *c, const float *W, const float *H)
             if (!std::isfinite(v)) return c->fail(PSGLD_E_ARG, "non-finite H");
             h[static_cast<size_t>(j) * Kp + k] = c->prior.mirror ? std::fabs(v) : v;
         }
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     HIPTRY(c, hipMemcpy(c->W[c->cur], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
     HIPTRY(c, hipMemcpy(c->H[c->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -1239,7 +1251,7 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
     if (c->t + n_iter >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
     if (n_iter == 0) return PSGLD_OK;
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     if ((s = ensure_eps_table(c, sched, c->t, c->t + n_iter))) return s;
     if (c->opt.persistent && c->dblocks_host.empty()) {
         psgld_ctx *one[1] = {c};
@@ -1296,7 +1308,7 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
             return c->fail(PSGLD_E_ARG, "batched contexts must share one device and one stream");
         max_n = std::max(max_n, n_iter[j]);
     }
-    HIPTRY(c0, hipSetDevice(c0->opt.device));
+    HIPTRY(c0, use_device(c0->opt.device));
     hipStream_t stream = c0->stream;
     std::vector<char> batched(n, 0);
     for (int32_t j = 0; j < n; ++j) {
@@ -1391,7 +1403,7 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
     for (int32_t k = 0; k < n; ++k)
         if (candidates[k] < 1) return c->fail(PSGLD_E_ARG, "candidates must be >= 1");
     psgld_status s;
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     int best = candidates[0];
     if (n > 1) {
         if ((s = check_schedule(c, sched))) return s;
@@ -1552,7 +1564,7 @@ psgld_status psgld_log_likelihood(psgld_ctx *c, double *ll)
     c->err.clear();
     if (!ll) return c->fail(PSGLD_E_ARG, "ll is required");
     if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     HIPTRY(c, launch_loglik(c->W[c->cur], c->H[c->cur], c->row_of_entry, c->ent_r, c->nnz_sparse, c->K, c->Kp,
                             c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials, c->ll_blocks, c->stream));
     const int nd = static_cast<int>(c->dblocks_host.size());
@@ -1642,7 +1654,7 @@ psgld_status psgld_set_state(psgld_ctx *c, const void *buf, size_t size)
     if (hdr[0] != kStateMagic || hdr[1] != kStateVersion || hdr[2] != c->I || hdr[3] != c->J ||
         hdr[4] != c->K || hdr[5] != c->B)
         return c->fail(PSGLD_E_ARG, "state was saved from a different problem");
-    HIPTRY(c, hipSetDevice(c->opt.device));
+    HIPTRY(c, use_device(c->opt.device));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     HIPTRY(c, hipMemcpy(c->W[c->cur], p, nw * sizeof(float), hipMemcpyHostToDevice));
     p += nw * sizeof(float);
@@ -1695,7 +1707,7 @@ void psgld_destroy(psgld_ctx *c)
 {
     if (!c) return;
     if (c->device_ready) {
-        (void)hipSetDevice(c->opt.device);
+        (void)use_device(c->opt.device);
         (void)hipStreamSynchronize(c->stream);
         drop_graphs(c);
         for (void *p : c->allocs) (void)hipFree(p);

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "runtime.hpp"
 #include "psgld.h"
 
 using namespace psgld;
@@ -277,7 +278,7 @@ psgld_status psgld_server_tick(psgld_server *srv, int32_t *n_running, int32_t *n
 {
     if (!srv) return PSGLD_E_ARG;
     srv->err.clear();
-    if (hipSetDevice(srv->opt.device) != hipSuccess) return srv->fail(PSGLD_E_DEVICE, "cannot select the device");
+    if (use_device(srv->opt.device) != hipSuccess) return srv->fail(PSGLD_E_DEVICE, "cannot select the device");
     // admission, in submission order
     while (!srv->queue.empty() && static_cast<int32_t>(srv->running.size()) < srv->opt.max_active) {
         Job *j = srv->queue.front();
@@ -409,7 +410,7 @@ const char *psgld_server_job_error(const psgld_server *srv, int64_t id)
 void psgld_server_destroy(psgld_server *srv)
 {
     if (!srv) return;
-    (void)hipSetDevice(srv->opt.device);
+    (void)use_device(srv->opt.device);
     (void)hipStreamSynchronize(srv->stream);
     for (auto &kv : srv->jobs)
         if (kv.second->ctx) psgld_destroy(kv.second->ctx);
