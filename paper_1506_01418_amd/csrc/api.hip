@@ -815,7 +815,8 @@ psgld_status step_persistent(psgld_ctx *const *ctxs, int n, int64_t n_iter, hipS
         for (int64_t done = 0; done < n_iter; done += kPersistentIters) {
             const int chunk = static_cast<int>(std::min(kPersistentIters, n_iter - done));
             HIPTRY(c0, launch_sparse_persistent(b, chunk, c0->lik_kind, c0->lpg, c0->qpl, 0, c0->barrier, stream));
-            HIPTRY(c0, launch_advance_clocks(clocks.data(), cnt, chunk, stream));
+            const std::vector<int32_t> delta(clocks.size(), chunk);
+            HIPTRY(c0, launch_advance_clocks(clocks.data(), delta.data(), cnt, stream));
         }
     }
     for (int j = 0; j < n; ++j) {
@@ -1353,20 +1354,27 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
         }
         return PSGLD_OK;
     }
+    // the batched contexts' clocks stay put during the call (launch k runs
+    // iteration clock + k) and advance once at its end
+    std::vector<int32_t *> clocks;
+    std::vector<int32_t> deltas;
+    for (int32_t j = 0; j < n; ++j)
+        if (batched[j]) {
+            clocks.push_back(ctxs[j]->clock);
+            deltas.push_back(static_cast<int32_t>(n_iter[j]));
+        }
     for (int64_t k = 0; k < max_n; ++k) {
         // one launch per kernel variant (lanes per group, quads per lane,
         // likelihood) and 64 contexts
         std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
-        std::vector<int32_t *> clocks;
         for (int32_t j = 0; j < n; ++j)
-            if (k < n_iter[j] && batched[j]) {
+            if (k < n_iter[j] && batched[j])
                 groups[std::make_tuple(ctxs[j]->lpg, ctxs[j]->qpl, ctxs[j]->lik_kind)].push_back(j);
-                clocks.push_back(ctxs[j]->clock);
-            }
         for (auto &g : groups) {
             const std::vector<int32_t> &js = g.second;
             for (size_t first = 0; first < js.size(); first += kMaxBatch) {
                 BatchArgs b{};
+                b.k = static_cast<int32_t>(k);
                 b.n = static_cast<int32_t>(std::min<size_t>(kMaxBatch, js.size() - first));
                 b.wg_first[0] = 0;
                 for (int32_t q = 0; q < b.n; ++q) {
@@ -1377,7 +1385,6 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
                 HIPTRY(c0, launch_sparse_batch(b, std::get<2>(g.first), std::get<0>(g.first), std::get<1>(g.first), stream));
             }
         }
-        if (!clocks.empty()) HIPTRY(c0, launch_advance_clocks(clocks.data(), static_cast<int>(clocks.size()), 1, stream));
         for (int32_t j = 0; j < n; ++j) {
             if (k >= n_iter[j]) continue;
             psgld_ctx *c = ctxs[j];
@@ -1387,9 +1394,12 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
             account_iteration(c, c->t);
             c->cur ^= 1;
             c->t += 1;
-            if (batched[j]) c->clock_host = c->t;
         }
     }
+    if (!clocks.empty())
+        HIPTRY(c0, launch_advance_clocks(clocks.data(), deltas.data(), static_cast<int>(clocks.size()), stream));
+    for (int32_t j = 0; j < n; ++j)
+        if (batched[j]) ctxs[j]->clock_host = ctxs[j]->t;
     return PSGLD_OK;
 }
 

@@ -173,12 +173,13 @@ struct BatchArgs {
     const JobDesc *jobs[kMaxBatch];
     int32_t wg_first[kMaxBatch + 1];
     int32_t n;
+    int32_t k;   // this launch runs iteration *clock + k of every context
 };
 
 hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lanes_per_group, int quads_per_lane,
                                hipStream_t stream);
-// *clocks[j] += delta for j < n.
-hipError_t launch_advance_clocks(int32_t *const *clocks, int n, int delta, hipStream_t stream);
+// *clocks[j] += delta[j] for j < n.
+hipError_t launch_advance_clocks(int32_t *const *clocks, const int32_t *delta, int n, hipStream_t stream);
 // n_iter iterations of the batch in one cooperative launch of `grid`
 // work-groups (<= 0: as many as the device holds at once, capped by the
 // work), with `barrier` (one device word, reset by the launch) as the

@@ -487,13 +487,14 @@ __device__ __forceinline__ int job_of(const int32_t *wg_first, int n, int v)
 }
 
 // Several contexts in one launch: the work-group finds its context, reads
-// the context's clock and runs its task of the current part.
+// the context's clock (iteration *clock + b.k; the clocks advance once after
+// a call's launches) and runs its task of that iteration's part.
 template <int LPG, int QPL, int LIK>
 __global__ __launch_bounds__(kBlockThreads) void sparse_batch_kernel(BatchArgs b)
 {
     const int j = job_of(b.wg_first, b.n, blockIdx.x);
     const JobDesc &d = *b.jobs[j];
-    job_task<LPG, QPL, LIK>(d, *d.clock, blockIdx.x - b.wg_first[j]);
+    job_task<LPG, QPL, LIK>(d, *d.clock + b.k, blockIdx.x - b.wg_first[j]);
 }
 
 // n_iter iterations of the contexts in one cooperative launch.  The grid is
@@ -545,13 +546,13 @@ __global__ void reset_barrier_kernel(uint32_t *barrier)
 
 struct ClockList {
     int32_t *clocks[kMaxBatch];
+    int32_t delta[kMaxBatch];
     int32_t n;
-    int32_t delta;
 };
 
 __global__ void advance_clocks_kernel(ClockList l)
 {
-    if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += l.delta;
+    if (static_cast<int>(threadIdx.x) < l.n) *l.clocks[threadIdx.x] += l.delta[threadIdx.x];
 }
 
 template <int LPG, int QPL>
@@ -696,13 +697,15 @@ hipError_t launch_sparse_persistent(const BatchArgs &b, int n_iter, int lik, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_advance_clocks(int32_t *const *clocks, int n, int delta, hipStream_t stream)
+hipError_t launch_advance_clocks(int32_t *const *clocks, const int32_t *delta, int n, hipStream_t stream)
 {
     for (int first = 0; first < n; first += kMaxBatch) {
         ClockList l{};
-        l.delta = delta;
         l.n = std::min(kMaxBatch, n - first);
-        for (int j = 0; j < l.n; ++j) l.clocks[j] = clocks[first + j];
+        for (int j = 0; j < l.n; ++j) {
+            l.clocks[j] = clocks[first + j];
+            l.delta[j] = delta[first + j];
+        }
         hipLaunchKernelGGL(advance_clocks_kernel, dim3(1), dim3(kMaxBatch), 0, stream, l);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
