@@ -1285,6 +1285,40 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     return PSGLD_OK;
 }
 
+namespace {
+
+// Auxiliary streams of a device for the kernel variants of a batched step,
+// with their fork and join events: created on first use and kept for the
+// life of the process (a stream costs about a millisecond to create).
+// Default priority, like every stream here.  Callers hold g_aux_mutex while
+// they enqueue on them.
+constexpr int kAuxStreams = 8;
+struct AuxStreams {
+    hipStream_t s[kAuxStreams] = {};
+    hipEvent_t join[kAuxStreams] = {};
+    hipEvent_t fork = nullptr;
+};
+std::mutex g_aux_mutex;
+std::map<int, AuxStreams> g_aux;
+
+psgld_status aux_streams(psgld_ctx *c, AuxStreams **out)
+{
+    auto it = g_aux.find(c->opt.device);
+    if (it == g_aux.end()) {
+        AuxStreams a;
+        HIPTRY(c, hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+        for (int i = 0; i < kAuxStreams; ++i) {
+            HIPTRY(c, hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking));
+            HIPTRY(c, hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming));
+        }
+        it = g_aux.emplace(c->opt.device, a).first;
+    }
+    *out = &it->second;
+    return PSGLD_OK;
+}
+
+}  // namespace
+
 psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *n_iter,
                               const psgld_eps_schedule *scheds)
 {
@@ -1358,11 +1392,30 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
     // iteration clock + k) and advance once at its end
     std::vector<int32_t *> clocks;
     std::vector<int32_t> deltas;
+    std::map<std::tuple<int, int, int>, int> variant;   // kernel variant -> its stream slot
     for (int32_t j = 0; j < n; ++j)
         if (batched[j]) {
             clocks.push_back(ctxs[j]->clock);
             deltas.push_back(static_cast<int32_t>(n_iter[j]));
+            variant.emplace(std::make_tuple(ctxs[j]->lpg, ctxs[j]->qpl, ctxs[j]->lik_kind), 0);
         }
+    // Variants touch disjoint contexts, so with more than one each runs on an
+    // auxiliary stream of its own (forked from and joined back into the
+    // contexts' stream), and the small launches of different variants overlap
+    // on the device instead of queueing behind each other.
+    std::unique_lock<std::mutex> aux_lock;
+    AuxStreams *aux = nullptr;
+    int n_aux = 0;
+    if (variant.size() > 1) {
+        aux_lock = std::unique_lock<std::mutex>(g_aux_mutex);
+        psgld_status s = aux_streams(c0, &aux);
+        if (s) return s;
+        n_aux = static_cast<int>(std::min<size_t>(variant.size(), kAuxStreams));
+        int slot = 0;
+        for (auto &v : variant) v.second = slot++ % n_aux;
+        HIPTRY(c0, hipEventRecord(aux->fork, stream));
+        for (int a = 0; a < n_aux; ++a) HIPTRY(c0, hipStreamWaitEvent(aux->s[a], aux->fork, 0));
+    }
     for (int64_t k = 0; k < max_n; ++k) {
         // one launch per kernel variant (lanes per group, quads per lane,
         // likelihood) and 64 contexts
@@ -1372,6 +1425,7 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
                 groups[std::make_tuple(ctxs[j]->lpg, ctxs[j]->qpl, ctxs[j]->lik_kind)].push_back(j);
         for (auto &g : groups) {
             const std::vector<int32_t> &js = g.second;
+            const hipStream_t gs = aux ? aux->s[variant.at(g.first)] : stream;
             for (size_t first = 0; first < js.size(); first += kMaxBatch) {
                 BatchArgs b{};
                 b.k = static_cast<int32_t>(k);
@@ -1382,7 +1436,7 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
                     b.jobs[q] = c->job_desc;
                     b.wg_first[q + 1] = b.wg_first[q] + c->max_tasks;
                 }
-                HIPTRY(c0, launch_sparse_batch(b, std::get<2>(g.first), std::get<0>(g.first), std::get<1>(g.first), stream));
+                HIPTRY(c0, launch_sparse_batch(b, std::get<2>(g.first), std::get<0>(g.first), std::get<1>(g.first), gs));
             }
         }
         for (int32_t j = 0; j < n; ++j) {
@@ -1395,6 +1449,10 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
             c->cur ^= 1;
             c->t += 1;
         }
+    }
+    for (int a = 0; a < n_aux; ++a) {
+        HIPTRY(c0, hipEventRecord(aux->join[a], aux->s[a]));
+        HIPTRY(c0, hipStreamWaitEvent(stream, aux->join[a], 0));
     }
     if (!clocks.empty())
         HIPTRY(c0, launch_advance_clocks(clocks.data(), deltas.data(), static_cast<int>(clocks.size()), stream));
