@@ -186,7 +186,12 @@ psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule
  * only coordinate-stored blocks are grouped by kernel variant (rank class and
  * likelihood branch) and up to 64 of them share one launch per iteration: the
  * launch reads a device table of the contexts, and each context's iteration
- * from its device clock.  Contexts with dense blocks are launched one by one
+ * from its device clock.  With more than one variant, each variant's launches
+ * go to an auxiliary stream of the library (a pool per device, kept for the
+ * life of the process), forked from the contexts' stream and joined back
+ * into it before the call returns, so the variants overlap on the device;
+ * work enqueued on the contexts' stream afterwards sees all of it.  Contexts
+ * with dense blocks are launched one by one
  * inside the same loop.  Each context's results are bitwise those of
  * psgld_step on it alone: the contexts share no memory.  All contexts must be
  * distinct and share one device and one stream (options.stream), else E_ARG;
