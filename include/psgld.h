@@ -50,7 +50,7 @@ typedef enum {
     PSGLD_E_NOMEM = -3,       /* host or device allocation failed */
     PSGLD_E_DEVICE = -4,      /* HIP runtime error, or no gfx950 device */
     PSGLD_E_NUMERIC = -5,     /* a non-finite value appeared in W or H */
-    PSGLD_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+    PSGLD_E_UNSUPPORTED = -6  /* valid request the library does not implement */
 } psgld_status;
 
 typedef struct psgld_ctx psgld_ctx;

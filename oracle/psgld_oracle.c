@@ -25,7 +25,7 @@
  *   - Monte Carlo averages after burn-in (Section 4.2.2): FP64 running sums
  *     of x and x^2 at kept iterations, and held-out predictive sums.
  *
- * Readings of points the paper leaves open (each is listed in the design doc):
+ * Readings of points the paper leaves open:
  *   N is the number of observed training entries and |Pi_t| the number of
  *   them inside the part; an empty part has scale 0.  eps_t = a (t0 + t)^-gamma
  *   generalises the paper's (a/t)^b.  For beta < 2 the mean is floored,
