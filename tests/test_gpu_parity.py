@@ -67,6 +67,10 @@ CASES = {
     "K30_gauss_mirror": lambda: workloads.random_sparse(400, 300, 20_000, 30, 5, beta=2.0,
                                                         prior="gaussian", mirror=True,
                                                         data_seed=15, chain_seed=16),
+    # four quads per lane over 8 lanes (32 quads) on rows of 96 floats: the
+    # last lanes' partner reads run past the row and are masked
+    "K68_B4": lambda: workloads.random_sparse(600, 500, 20_000, 68, 4, beta=2.0, phi=0.5, zipf_a=1.0,
+                                              data_seed=19, chain_seed=20),
     # general beta (no closed-form branch) with 4 lanes of one quad each
     "K12_beta07_B5": lambda: workloads.random_sparse(500, 420, 25_000, 12, 5, beta=0.7,
                                                      prior="exponential", mirror=True, zipf_a=1.0,
