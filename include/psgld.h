@@ -147,14 +147,15 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B,
  * beta <= 1 and val > 0 when beta <= 0.  Cells absent from the list are
  * missing (not zero).  Duplicated (row, col) pairs are E_ARG.  Builds the
  * block-sorted layout on the host and uploads it.  Once per context
- * (E_STATE on a second load).  nnz >= 0 and below 2^31. */
+ * (E_STATE on a second load).  0 <= nnz <= 2^31 - 64. */
 psgld_status psgld_load_coo(psgld_ctx *ctx, int64_t nnz, const int32_t *row,
                             const int32_t *col, const float *val);
 
 /* Loads a dense I x J row-major value matrix V with a training mask
  * (1 = observed training cell, 0 = missing; NULL = every cell observed).
  * Blocks whose training density exceeds options.dense_threshold are run by
- * the dense kernel, the rest as coordinates.  Same value rules as load_coo. */
+ * the dense kernel, the rest as coordinates (E_ARG if those exceed 2^31 - 64
+ * cells).  Same value rules as load_coo. */
 psgld_status psgld_load_dense(psgld_ctx *ctx, const float *V, const uint8_t *train_mask);
 
 /* Held-out cells whose posterior-mean prediction is tracked: at every

@@ -42,6 +42,9 @@ thread_local std::string g_create_error;
 constexpr uint32_t kStateMagic = 0x50534744u;  // "PSGD"
 constexpr uint32_t kStateVersion = 1;
 constexpr int kDenseLLPerBlock = 16;   // work-groups per dense block in the log-likelihood
+// Training entries held as coordinates: the kernels index the entry arrays
+// with 32-bit integers, up to a batch and the padding past the last entry.
+constexpr int64_t kMaxEntries = INT32_MAX - 64;
 
 bool is_gfx950(int device)
 {
@@ -376,6 +379,8 @@ void remember_entries_per_group(const psgld_ctx *c, int value)
 psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const int32_t *col,
                           const float *val)
 {
+    if (nnz < 0 || nnz > kMaxEntries)
+        return c->fail(PSGLD_E_ARG, "at most 2^31 - 64 training entries are held as coordinates");
     const int64_t I = c->I, J = c->J;
     const int32_t B = c->B;
     // bucket by (part, row) and by (part, column): counting sort
@@ -951,7 +956,7 @@ psgld_status psgld_load_coo(psgld_ctx *c, int64_t nnz, const int32_t *row, const
     if (!c) return PSGLD_E_ARG;
     c->err.clear();
     if (c->loaded) return c->fail(PSGLD_E_STATE, "data already loaded");
-    if (nnz < 0 || nnz >= INT32_MAX) return c->fail(PSGLD_E_ARG, "nnz must be in [0, 2^31)");
+    if (nnz < 0 || nnz > kMaxEntries) return c->fail(PSGLD_E_ARG, "nnz must be in [0, 2^31 - 64]");
     if (nnz > 0 && (!row || !col || !val)) return c->fail(PSGLD_E_ARG, "row, col and val are required");
     psgld_status s;
     if ((s = check_coords(c, nnz, row, col))) return s;

@@ -78,6 +78,13 @@ def test_load_validates_on_host_before_device():
     with pytest.raises(pkg.PsgldError) as e:
         pkg.psgld_step(s.ctx, 1, pkg.psgld_eps_schedule(1e-3, 1.0, 0.3))
     assert e.value.status == pkg.PSGLD_E_ARG
+    # entry counts whose 32-bit entry indices (plus a batch and the padding
+    # read past the last entry) would overflow are refused before any pointer
+    # is read
+    for nnz in (-1, 2**31 - 63, 2**31):
+        with pytest.raises(pkg.PsgldError, match=r"nnz must be in \[0, 2\^31 - 64\]") as e:
+            pkg._check(pkg.lib().psgld_load_coo(s.ctx, nnz, None, None, None), s.ctx)
+        assert e.value.status == pkg.PSGLD_E_ARG
     s.close()
     g.close()
 
