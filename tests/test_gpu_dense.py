@@ -158,3 +158,21 @@ def test_bf16_chain_matches_fp32_heldout_rmse():
     f32, bf16 = rmse[pkg.PSGLD_FP32], rmse[pkg.PSGLD_BF16_DENSE]
     assert abs(bf16 - f32) / f32 <= 0.01, (f32, bf16)
     assert f32 < rmse0 and bf16 < rmse0, (f32, bf16, rmse0)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_dense_1000_iterations_rmse_parity(bf16):
+    """The Poisson NMF chain of 256 x 256 (K = 8, B = 4) for 1000 iterations
+    with burn-in 500, every block on the dense kernels: held-out RMSE of the
+    posterior-mean predictor within 1% of the oracle's, with FP32 and with
+    BF16 operands."""
+    wl = workloads.dense_poisson(T=1000, burn_in=500)
+    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_min_cols=1)
+    s.step(wl.T, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    ch = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+    ch.run(wl.T)
+    assert s.num_samples() == ch.n_kept == 500
+    g, r = s.heldout_rmse(), ch.heldout_rmse(wl.hval)
+    s.close()
+    assert abs(g - r) <= 0.01 * r, (g, r)

@@ -181,6 +181,30 @@ def test_dense_poisson_200_iterations_rmse_parity():
     assert abs(g - r) / r <= 0.01, (g, r)
 
 
+@pytest.mark.parametrize("case", [
+    dict(I=1500, J=800, nnz=100_000, K=20, B=8, beta=2.0, zipf_a=1.0),
+    dict(I=1200, J=900, nnz=80_000, K=16, B=6, beta=1.0, prior="exponential", mirror=True, zipf_a=1.0),
+], ids=["gauss_K20_B8", "kl_K16_B6"])
+def test_1000_iterations_rmse_parity(case):
+    """1000 iterations with burn-in 500 and thinning 5 (Zipf-skewed columns):
+    held-out RMSE of the posterior-mean predictor within 1% of the oracle's,
+    and below the RMSE of the initial factors."""
+    a = dict(case)
+    I, J, nnz, K, B = (a.pop(k) for k in ("I", "J", "nnz", "K", "B"))
+    wl = workloads.random_sparse(I, J, nnz, K, B, data_seed=31, chain_seed=32, T=1000, burn_in=500, thin=5, **a)
+    s = pkg.PSGLD.from_workload(wl)
+    s.step(wl.T, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    ch = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+    ch.run(wl.T)
+    assert s.num_samples() == ch.n_kept == 100
+    g, r = s.heldout_rmse(), ch.heldout_rmse(wl.hval)
+    s.close()
+    mu0 = np.einsum("nk,kn->n", wl.W0[wl.hrow].astype(np.float64), wl.H0[:, wl.hcol].astype(np.float64))
+    r0 = float(np.sqrt(np.mean((wl.hval - mu0) ** 2)))
+    assert abs(g - r) <= 0.01 * r, (g, r)
+    assert r < r0 and g < r0, (g, r, r0)
+
+
 def test_log_likelihood_matches_oracle():
     wl = CASES["cpois_K64_B16"]()
     s = pkg.PSGLD.from_workload(wl)
