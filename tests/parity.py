@@ -1,4 +1,6 @@
 """Shared helpers of the GPU-vs-oracle parity tests (not a test module)."""
+import os
+
 import numpy as np
 
 import oracle
@@ -46,3 +48,13 @@ def step_parity(wl, steps_before=0, flags=0, sampler=None, dense=False, **overri
     eW = scaled_error(Wn, ch.W, bW)
     eH = scaled_error(Hn, ch.H, bH)
     return max(float(eW.max(initial=0)), float(eH.max(initial=0))), s
+
+
+def philox_kat():
+    """The published known-answer vectors of Philox4x32-10 (Salmon et al.,
+    SC'11), from tests/golden: inputs (ctr0..3, key0..1) and outputs."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+    rows = [[int(x, 16) for x in line.split()] for line in open(path) if line.strip() and line[0] != "#"]
+    rows = np.array(rows, dtype=np.uint64).astype(np.uint32)
+    assert rows.shape == (3, 10)
+    return rows[:, :6], rows[:, 6:]

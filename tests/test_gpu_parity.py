@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_1506_01418_amd as pkg
 import workloads
-from parity import TOL_FP32, oracle_config, scaled_error, step_parity
+from parity import TOL_FP32, oracle_config, philox_kat, scaled_error, step_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +27,12 @@ def test_philox_blocks_bit_exact():
     got = pkg.psgld_philox_blocks(ctr, key)
     for c, k, g in zip(ctr, key, got):
         assert np.array_equal(oracle.philox4x32_10(c, k), g)
+
+
+def test_philox_blocks_known_answer_vectors():
+    inp, expect = philox_kat()
+    got = pkg.psgld_philox_blocks(inp[:, :4], inp[:, 4:])
+    assert np.array_equal(got, expect), (got, expect)
 
 
 def test_normals_match_oracle():

@@ -2,8 +2,10 @@
 
 The noise of Eq. (8)-(9) is N(0, 2 eps) per parameter.  The oracle draws it
 from Philox4x32-10 (Salmon et al., SC'11).  Pins:
-  * raw 128-bit blocks agree bit for bit with an independent implementation,
-    rocRAND's Philox4x32-10 engine, run as a black box on the host;
+  * raw 128-bit blocks equal the generator's published known-answer vectors
+    (tests/golden/philox4x32_10_kat.txt) and agree bit for bit with an
+    independent implementation, rocRAND's Philox4x32-10 engine, run as a
+    black box on the host;
   * the uniforms are in (0, 1) and the normals pass mean / variance /
     Kolmogorov-Smirnov tests against N(0, 1), with adjacent counters
     uncorrelated.
@@ -18,6 +20,7 @@ import pytest
 from scipy import stats
 
 import oracle
+from parity import philox_kat
 
 ROCRAND_PROBE = r"""
 #include <hip/hip_runtime.h>
@@ -75,6 +78,12 @@ def test_philox_matches_rocrand_engine():
     for c, g in zip(cases, got):
         mine = oracle.philox4x32_10(c[:4], c[4:])
         assert np.array_equal(mine.astype(np.uint64), g), (c, mine, g)
+
+
+def test_philox_known_answer_vectors():
+    inp, expect = philox_kat()
+    for c, e in zip(inp, expect):
+        assert np.array_equal(oracle.philox4x32_10(c[:4], c[4:]), e), (c, e)
 
 
 def test_normals_are_standard_gaussian():
