@@ -158,8 +158,8 @@ __device__ __forceinline__ ItemStart<QPL> start_item(const SparseIterArgs &a, co
 // one is reduced).  Quads past ceil(K/4) have x = 0 and read up to one row
 // ahead (the factor arrays are padded and zero-initialised); a batch's
 // records past s1 belong to the next item or to the padding of the entry
-// array, so their partner reads stay in bounds and only their contributions
-// are masked.  A short item is thus one round of partner loads.
+// array; in the last batch their partner rows are not loaded and their
+// contributions are masked.  A short item is thus one round of partner loads.
 template <int LPG, int QPL, int LIK>
 __device__ __forceinline__ void item_gradient(const SparseIterArgs &a, const WgTask &task, const GroupRec &rec,
                                               const ItemStart<QPL> &st, int lane, float4 (&acc)[QPL])
@@ -203,11 +203,14 @@ __device__ __forceinline__ void item_gradient(const SparseIterArgs &a, const WgT
     }
     const int n = s1 - e;   // 0 .. U - 1 entries left
     if (n > 0) {
+        // the records past s1 load no partner row (their lanes are masked
+        // off), which spares the L2 the requests of short items
         float4 o[U][QPL];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int m = 0; m < QPL; ++m) o[u][m] = load4(other_lane + cur[u].off + 4 * m * LPG);
+            for (int m = 0; m < QPL; ++m)
+                o[u][m] = u < n ? load4(other_lane + cur[u].off + 4 * m * LPG) : make_float4(0.f, 0.f, 0.f, 0.f);
         float mu[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
