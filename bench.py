@@ -75,35 +75,52 @@ class HipEvents:
         assert self.hip.hipDeviceSynchronize() == 0
 
 
-def algorithmic_bytes(wl, n_p, ho_p, t, p):
-    """Bytes one iteration must move at minimum: each training entry of the
-    part read once (4-byte index + 4-byte value), every factor element read
-    and written once in FP32, the FP64 sums of x and x^2 read and written at
-    kept iterations, one FP64 read-modify-write per held-out cell of the part
-    after burn-in.  p is the part of iteration t."""
-    b = 8 * n_p[p] + 8 * (wl.I + wl.J) * wl.K
-    if t >= wl.burn_in:
-        b += 16 * ho_p[p]
-        if (t - wl.burn_in) % wl.thin == 0:
-            b += 32 * (wl.I + wl.J) * wl.K
-    return b
+# The library's default placement of the blocks of a dense load: a block
+# runs on the dense kernels when it has at most 128 rows, at least 256
+# columns, K <= 64 and a training density above 0.3 (contiguous pieces);
+# every other block runs as coordinates.
+DENSE_MAX_ROWS, DENSE_MIN_COLS, DENSE_MAX_K, DENSE_THRESHOLD = 128, 256, 64, 0.3
 
 
-def dense_part_cells(wl):
-    """Cells (all, masked or not) of each part's blocks: the dense kernels
-    stream every cell of a dense block."""
-    rp = np.bincount(pkg_pieces(wl, "row"), minlength=wl.B)
-    cp = np.bincount(pkg_pieces(wl, "col"), minlength=wl.B)
-    return np.array([sum(int(rp[b]) * int(cp[(b + p) % wl.B]) for b in range(wl.B)) for p in range(wl.B)])
+def block_placement(wl):
+    """(dense, cnt, rows, cols): which blocks (b, c) run on the dense kernels,
+    the training entries of every block and the sizes of the pieces."""
+    rp, cp = pkg_pieces(wl, "row"), pkg_pieces(wl, "col")
+    rows, cols = np.bincount(rp, minlength=wl.B), np.bincount(cp, minlength=wl.B)
+    cnt = np.zeros((wl.B, wl.B), dtype=np.int64)
+    np.add.at(cnt, (rp[wl.row], cp[wl.col]), 1)
+    size = rows[:, None].astype(np.float64) * cols[None, :]
+    dense = ((rows[:, None] <= DENSE_MAX_ROWS) & (cols[None, :] >= DENSE_MIN_COLS) & (wl.K <= DENSE_MAX_K)
+             & (cnt > DENSE_THRESHOLD * size))
+    return dense, cnt, rows, cols
 
 
-def dense_algorithmic(wl, cells_p, ho_p, t, p):
-    """(bytes, flops) of one dense iteration: every cell of the part's blocks
-    read once (FP32 value + mask byte), factors read and written once in
-    FP32, FP64 sums at kept iterations, FP64 held-out sums after burn-in; 6K
-    flops per cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the part
+def part_work(wl, dense, cnt, rows, cols):
+    """Per part p: cells of its dense-kernel blocks (all cells, masked or
+    not: the dense kernels stream every cell) and training entries of its
+    blocks that run as coordinates."""
+    cells = np.zeros(wl.B, dtype=np.int64)
+    entries = np.zeros(wl.B, dtype=np.int64)
+    for p in range(wl.B):
+        for b in range(wl.B):
+            c = (b + p) % wl.B
+            if dense[b, c]:
+                cells[p] += int(rows[b]) * int(cols[c])
+            else:
+                entries[p] += int(cnt[b, c])
+    return cells, entries
+
+
+def algorithmic_cost(wl, cells_p, entries_p, ho_p, t, p):
+    """(bytes, flops) one iteration must move and compute at minimum: each
+    training entry of the part's coordinate blocks read once (4-byte index +
+    4-byte value), each cell of its dense blocks read once (FP32 value + mask
+    byte), every factor element read and written once in FP32, the FP64 sums
+    of x and x^2 read and written at kept iterations, one FP64
+    read-modify-write per held-out cell of the part after burn-in; 6K flops
+    per dense cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the part
     of iteration t."""
-    b = 5 * cells_p[p] + 8 * (wl.I + wl.J) * wl.K
+    b = 5 * cells_p[p] + 8 * entries_p[p] + 8 * (wl.I + wl.J) * wl.K
     if t >= wl.burn_in:
         b += 16 * ho_p[p]
         if (t - wl.burn_in) % wl.thin == 0:
@@ -340,14 +357,23 @@ def main():
                                 persistent=args.persistent, part_order=args.part_order, **pieces)
     print(f"[bench] loaded in {time.perf_counter() - t_load:.1f} s", file=sys.stderr, flush=True)
     stream = s.stream()
+    n_p, N = s.part_sizes()
+    if dense:
+        placed, cnt, rows, cols = block_placement(wl)
+        cells_p, entries_p = part_work(wl, placed, cnt, rows, cols)
+        # the blocks' entries per part agree with the library's part sizes
+        assert np.array_equal([sum(int(cnt[b, (b + p) % wl.B]) for b in range(wl.B)) for p in range(wl.B)], n_p)
+    else:
+        placed = np.zeros((wl.B, wl.B), dtype=bool)
+        cells_p, entries_p = np.zeros(wl.B, dtype=np.int64), np.asarray(n_p, dtype=np.int64)
+    runs_dense, runs_sparse = bool(placed.any()), not bool(placed.all())
     chosen = None
-    if not dense:
+    if runs_sparse:
         t_tune = time.perf_counter()
         cands = (args.entries_per_group,) if args.entries_per_group > 0 else (16, 32, 64, 128)
         chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=cands, iters=wl.B)
         print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
               file=sys.stderr, flush=True)
-    n_p, N = s.part_sizes()
     rpc = pieces.get("row_piece", pkg_pieces(wl, "row"))
     cpc = pieces.get("col_piece", pkg_pieces(wl, "col"))
     ho_part = (np.asarray(cpc)[wl.hcol] - np.asarray(rpc)[wl.hrow]) % wl.B
@@ -392,33 +418,30 @@ def main():
     post = durs[min(args.steps, wl.burn_in):]
     print(f"[bench] launch average before burn-in {pre.mean() * 1e3:.2f} us"
           + (f", after {post.mean() * 1e3:.2f} us" if len(post) else ""), file=sys.stderr, flush=True)
-    if dense:
-        cells_p = dense_part_cells(wl)
-        bf = np.array([dense_algorithmic(wl, cells_p, ho_p, t, parts[t]) for t in range(args.steps)],
-                      dtype=np.float64)
-        alg, flops = bf[:, 0], bf[:, 1]
-        t_hbm = alg.mean() / (HBM_PEAK_GBS * 1e9)
-        t_mfma = flops.mean() / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
-        if t_mfma > t_hbm:
-            achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
-            roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[args.precision],
-                    "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[args.precision]}
-        else:
-            achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS}
-        roof.update({"traffic": measured_traffic(f"{wl.name}:{args.precision}", "dense"),
-                     "kernel": "dense iteration (dense_tile_kernel + dense_w_update_kernel)",
-                     "avg_launch_us": avg_ms * 1e3,
-                     "alg_bytes_per_launch": float(alg.mean()), "flops_per_launch": float(flops.mean())})
+    bf = np.array([algorithmic_cost(wl, cells_p, entries_p, ho_p, t, parts[t]) for t in range(args.steps)],
+                  dtype=np.float64)
+    alg, flops = bf[:, 0], bf[:, 1]
+    t_hbm = alg.mean() / (HBM_PEAK_GBS * 1e9)
+    t_mfma = flops.mean() / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
+    if t_mfma > t_hbm:
+        achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[args.precision],
+                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[args.precision]}
     else:
-        alg = np.array([algorithmic_bytes(wl, n_p, ho_p, t, parts[t]) for t in range(args.steps)],
-                       dtype=np.float64)
         achieved = float(alg.mean()) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl.name, "sparse"),
-                "kernel": "sparse_iter_kernel",
-                "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": float(alg.mean())}
+                "frac": achieved / HBM_PEAK_GBS}
+    if runs_dense and not runs_sparse:
+        kernel, traffic = ("dense iteration (dense_tile_kernel + dense_w_update_kernel)",
+                           measured_traffic(f"{wl.name}:{args.precision}", "dense"))
+    elif runs_dense:
+        kernel, traffic = "dense iteration and sparse_iter_kernel", None
+    else:
+        kernel, traffic = "sparse_iter_kernel", measured_traffic(wl.name, "sparse")
+    roof.update({"traffic": traffic, "kernel": kernel, "avg_launch_us": avg_ms * 1e3,
+                 "alg_bytes_per_launch": float(alg.mean())})
+    if runs_dense:
+        roof["flops_per_launch"] = float(flops.mean())
     print(f"[bench] pass 2: iteration avg {avg_ms * 1e3:.2f} us, roofline {roof['achieved']:.1f} "
           f"{roof['unit']} ({roof['bound']}), RMSE {rmse2}", file=sys.stderr, flush=True)
     s.close()
@@ -434,15 +457,16 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed_ms / args.steps,
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": value / PAPER_UPDATES_PER_S[wl.name] if wl.name in PAPER_UPDATES_PER_S else None,
-        "dtype": "bf16+f32" if dense and args.precision == "bf16" else "f32",
+        "dtype": "bf16+f32" if runs_dense and args.precision == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
                    "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
-                   "heldout_rmse": rmse, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": dense,
-                   "precision": args.precision if dense else "f32", "parallelism": "single-gpu",
+                   "heldout_rmse": rmse, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": runs_dense,
+                   "dense_blocks": int(placed.sum()),
+                   "precision": args.precision if runs_dense else "f32", "parallelism": "single-gpu",
                    "part_order": args.part_order, "balanced_pieces": bool(pieces),
-                   "launch": "persistent" if args.persistent and not dense else
+                   "launch": "persistent" if args.persistent and not runs_dense else
                              ("graph" if args.graph_iters >= 0 else "per-iteration")},
         "roofline": roof,
         "cpu_baseline": cpu,
