@@ -474,12 +474,15 @@ def main():
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         import torch
+        # the fill kernel of torch.ones only writes; the reference is the neg
+        # dispatch after it, so the two must not be averaged together
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         torch.neg(src, out=dst)      # an elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
-        print("[bench] calibration copy: 268435456 bytes read and written", file=sys.stderr, flush=True)
+        print("[bench] calibration copy (the neg kernel, after a fill): 268435456 bytes read and written",
+              file=sys.stderr, flush=True)
 
 
 def pkg_pieces(wl, which):
