@@ -53,3 +53,22 @@ def test_algorithmic_cost_counts_cells_entries_and_extras():
     assert not cells.any() and entries.sum() == wl.nnz
     assert bench.algorithmic_cost(wl, cells, entries, np.zeros(32, int), 0, 3) == (
         8 * entries[3] + 8 * (wl.I + wl.J) * wl.K, 0)
+
+
+def test_traffic_copy_reference_reproduces_the_copy():
+    """The stored copy reference scales its own counters back to the bytes the
+    copy moves (256 MiB read, 256 MiB written), and every stored run is priced
+    with it: read and write bytes both positive, the read scale between the
+    64- and 128-byte request sizes FETCH_SIZE can mistake."""
+    import json
+    with open(os.path.join(_ROOT, "profiles", "traffic.json")) as f:
+        data = json.load(f)
+    ref = data["copy_reference"]
+    assert abs(ref["FETCH_SIZE_KiB"] * ref["fetch_scale"] - 262144.0) < 1.0
+    assert abs(ref["WRITE_SIZE_KiB"] * ref["write_scale"] - 262144.0) < 1.0
+    assert 1.0 <= ref["fetch_scale"] <= 2.0 + 1e-3
+    for key, run in data["runs"].items():
+        kind = "dense" if key.startswith("dense") else "sparse"
+        want = 1024.0 * (run["FETCH_SIZE_KiB"] * ref["fetch_scale"] + run["WRITE_SIZE_KiB"] * ref["write_scale"])
+        got = bench.measured_traffic(key, kind)
+        assert got is None or abs(got - want) < 1.0
