@@ -1060,7 +1060,7 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
             blk.n_tiles = (blk.n + wg_cols - 1) / wg_cols;
             const int32_t idx_in_part = static_cast<int32_t>(c->dblocks_host.size() - c->dblk_off[p]);
             for (int32_t tt = 0; tt < blk.n_tiles; ++tt)
-                tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, {0, 0, 0, 0, 0}});
+                tiles.push_back(DenseTile{idx_in_part, tt * wg_cols, partial + tt, {}});
             partial += blk.n_tiles;
             for (int64_t i = 0; i < blk.m; ++i) {
                 for (int64_t j = 0; j < blk.n; ++j) {
