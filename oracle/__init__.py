@@ -31,8 +31,9 @@ PRIOR_KINDS = {"exponential": 0, "gaussian": 1}
 
 
 def build() -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    """Compile the oracle with gcc (no fast-math, no FMA contraction; OpenMP
+    threads over the blocks of a part and the rows/columns of the sweep)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
            "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -88,6 +89,14 @@ def lib():
         L.oracle_loglik.restype = C.c_int
         L.oracle_run.argtypes = [C.POINTER(_Cfg), C.POINTER(_State), C.c_int64, _P, _P]
         L.oracle_run.restype = C.c_int
+        L.oracle_prepare.argtypes = [C.POINTER(_Cfg), C.POINTER(_State)]
+        L.oracle_prepare.restype = _P
+        L.oracle_release.argtypes = [_P]
+        L.oracle_release.restype = None
+        L.oracle_run_prepared.argtypes = [C.POINTER(_Cfg), C.POINTER(_State), _P, C.c_int64, _P, _P]
+        L.oracle_run_prepared.restype = C.c_int
+        L.oracle_threads.argtypes = [C.c_int]
+        L.oracle_threads.restype = C.c_int
         L.oracle_part_at.argtypes = [C.POINTER(_Cfg), C.c_int64, _P, C.c_int64]
         L.oracle_part_at.restype = C.c_int32
         _lib = L
@@ -126,6 +135,12 @@ def partition(n: int, B: int) -> np.ndarray:
 
 def dbeta(v: float, mu: float, beta: float) -> float:
     return lib().oracle_dbeta(float(v), float(mu), float(beta))
+
+
+def threads(n: int = 0) -> int:
+    """Sets the oracle's thread count when n >= 1; returns the count in use.
+    Results do not depend on it (bitwise)."""
+    return int(lib().oracle_threads(int(n)))
 
 
 # ---------------------------------------------------------------- the chain
@@ -192,6 +207,19 @@ class Chain:
         self.n_kept = 0
         self.ho_sum = np.zeros(len(self.hrow))
         self.ho_cnt = np.zeros(len(self.hrow), dtype=np.int64)
+        self._prep = None   # bucketing of the entries by (part, block), made on first run
+
+    def __del__(self):
+        if getattr(self, "_prep", None):
+            lib().oracle_release(self._prep)
+            self._prep = None
+
+    def _prepared(self):
+        if self._prep is None:
+            self._prep = lib().oracle_prepare(C.byref(self.cfg.c()), C.byref(self._state()))
+            if not self._prep:
+                raise ValueError("oracle_prepare failed (invalid input or out of memory)")
+        return self._prep
 
     def _state(self) -> _State:
         return _State(len(self.row), _ptr(self.row), _ptr(self.col), _ptr(self.val),
@@ -212,7 +240,8 @@ class Chain:
         st = self._state()
         bW = np.zeros_like(self.W) if bounds else None
         bH = np.zeros_like(self.H) if bounds else None
-        rc = lib().oracle_run(C.byref(self.cfg.c()), C.byref(st), n_iter, _ptr(bW), _ptr(bH))
+        rc = lib().oracle_run_prepared(C.byref(self.cfg.c()), C.byref(st), self._prepared(), n_iter,
+                                       _ptr(bW), _ptr(bH))
         self.t = st.t
         self.n_kept = st.n_kept
         if rc != 0:

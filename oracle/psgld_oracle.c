@@ -25,6 +25,12 @@
  *   - Monte Carlo averages after burn-in (Section 4.2.2): FP64 running sums
  *     of x and x^2 at kept iterations, and held-out predictive sums.
  *
+ * Threads (OpenMP): the B blocks of a part share no row and no column
+ * (Definition 2), so their gradient sums run on different threads, and the
+ * rows of W and columns of H are stepped independently.  Every sum keeps
+ * the same terms in the same order whatever the thread count, so results
+ * are bitwise independent of it.
+ *
  * Readings of points the paper leaves open:
  *   N is the number of observed training entries and |Pi_t| the number of
  *   them inside the part; an empty part has scale 0.  eps_t = a (t0 + t)^-gamma
@@ -34,6 +40,7 @@
  *   (k/4, row-or-column index, t, stream), then Box-Muller.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -238,44 +245,82 @@ double oracle_eps(const oracle_cfg *c, int64_t t)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Entry bookkeeping: training entries bucketed by part, each bucket in      */
-/* (i, j) lexicographic order.                                              */
+/* Entry bookkeeping.  Training entries are put in (i, j) lexicographic      */
+/* order (two stable counting sorts: by column, then by row), then bucketed  */
+/* stably by (part p, block b) where block b of part p is (b, (b+p) mod B):  */
+/* every bucket lists one block's entries in (i, j) order.  Held-out cells   */
+/* are bucketed the same way.  The bucketing depends only on the data and   */
+/* the pieces, so a chain prepares it once (oracle_prepare).                 */
 /* ------------------------------------------------------------------------ */
-typedef struct {
-    int64_t *order;     /* entry ids, grouped by part, lexicographic inside */
-    int64_t *part_beg;  /* B+1 offsets into order */
-    int64_t *ho_order;  /* held-out ids grouped by part */
-    int64_t *ho_beg;
-} buckets;
+/* Loops with less work than this many elements run on the calling thread
+ * (forking threads costs more than they save on small problems). */
+#define OR_PAR_MIN 32768
 
-static const int32_t *g_row, *g_col;
-static int cmp_entry(const void *a, const void *b)
+struct oracle_prep {
+    int32_t B;
+    int64_t *order;     /* entry ids, bucket-major, (i, j) order inside */
+    int64_t *beg;       /* B*B+1 offsets: bucket p*B + b */
+    int64_t *ho_order;  /* held-out ids, same bucketing */
+    int64_t *ho_beg;
+    int64_t *n_part;    /* |Pi_p| for every part */
+};
+typedef struct oracle_prep oracle_prep;
+
+/* Part p holds block (b, (b+p) mod B) for every b, so entry (i,j) belongs to
+ * part (col_piece - row_piece) mod B and, inside it, to block b = row_piece. */
+static int64_t bucket_of(const int32_t *rp, const int32_t *cp, int32_t B, int32_t i, int32_t j)
 {
-    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
-    if (g_row[x] != g_row[y]) return g_row[x] < g_row[y] ? -1 : 1;
-    if (g_col[x] != g_col[y]) return g_col[x] < g_col[y] ? -1 : 1;
-    return 0;
+    return (int64_t)part_of_entry(rp[i], cp[j], B) * B + rp[i];
 }
 
-static int bucket_by_part(const oracle_cfg *c, const int32_t *rp, const int32_t *cp, int64_t n,
-                          const int32_t *row, const int32_t *col, int64_t **order_out,
-                          int64_t **beg_out)
+/* Stable counting sort of the ids in[0..n) by key[id] in [0, nkey). */
+static int counting_sort(const int64_t *in, int64_t n, const int32_t *key, int64_t nkey, int64_t *out)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)nkey + 1, sizeof(int64_t));
+    if (!cnt) return OR_ENOMEM;
+    for (int64_t m = 0; m < n; ++m) cnt[key[in[m]] + 1]++;
+    for (int64_t k = 0; k < nkey; ++k) cnt[k + 1] += cnt[k];
+    for (int64_t m = 0; m < n; ++m) out[cnt[key[in[m]]]++] = in[m];
+    free(cnt);
+    return OR_OK;
+}
+
+static int bucket_entries(const oracle_cfg *c, const int32_t *rp, const int32_t *cp, int64_t n,
+                          const int32_t *row, const int32_t *col, int64_t **order_out, int64_t **beg_out)
 {
     int32_t B = c->B;
+    int64_t nb = (int64_t)B * B;
+    int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    int64_t *beg = (int64_t *)calloc((size_t)B + 1, sizeof(int64_t));
-    if (!order || !beg) { free(order); free(beg); return OR_ENOMEM; }
-    for (int64_t e = 0; e < n; ++e) beg[part_of_entry(rp[row[e]], cp[col[e]], B) + 1]++;
-    for (int32_t p = 0; p < B; ++p) beg[p + 1] += beg[p];
-    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);
-    if (!fill) { free(order); free(beg); return OR_ENOMEM; }
-    memcpy(fill, beg, sizeof(int64_t) * (size_t)B);
-    for (int64_t e = 0; e < n; ++e) order[fill[part_of_entry(rp[row[e]], cp[col[e]], B)]++] = e;
-    free(fill);
-    g_row = row; g_col = col;
-    for (int32_t p = 0; p < B; ++p)
-        qsort(order + beg[p], (size_t)(beg[p + 1] - beg[p]), sizeof(int64_t), cmp_entry);
-    *order_out = order; *beg_out = beg;
+    int64_t *beg = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
+    int rc = (ids && tmp && order && beg) ? OR_OK : OR_ENOMEM;
+    if (rc == OR_OK) {
+        for (int64_t e = 0; e < n; ++e) ids[e] = e;
+        rc = counting_sort(ids, n, col, c->J, tmp);            /* by column ... */
+        if (rc == OR_OK) rc = counting_sort(tmp, n, row, c->I, ids);   /* ... then by row: (i, j) order */
+    }
+    if (rc == OR_OK) {
+        for (int64_t m = 0; m < n; ++m) beg[bucket_of(rp, cp, B, row[ids[m]], col[ids[m]]) + 1]++;
+        for (int64_t k = 0; k < nb; ++k) beg[k + 1] += beg[k];
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+        if (!fill) {
+            rc = OR_ENOMEM;
+        } else {
+            memcpy(fill, beg, sizeof(int64_t) * (size_t)nb);
+            for (int64_t m = 0; m < n; ++m) order[fill[bucket_of(rp, cp, B, row[ids[m]], col[ids[m]])]++] = ids[m];
+            free(fill);
+        }
+    }
+    free(ids);
+    free(tmp);
+    if (rc != OR_OK) {
+        free(order);
+        free(beg);
+        return rc;
+    }
+    *order_out = order;
+    *beg_out = beg;
     return OR_OK;
 }
 
@@ -292,6 +337,44 @@ static int check_inputs(const oracle_cfg *c, const oracle_state *s)
     return OR_OK;
 }
 
+void oracle_release(oracle_prep *pr)
+{
+    if (!pr) return;
+    free(pr->order);
+    free(pr->beg);
+    free(pr->ho_order);
+    free(pr->ho_beg);
+    free(pr->n_part);
+    free(pr);
+}
+
+/* Buckets the training entries and held-out cells of s under c's pieces.
+ * Returns NULL on invalid input or when memory runs out. */
+oracle_prep *oracle_prepare(const oracle_cfg *c, const oracle_state *s)
+{
+    if (check_inputs(c, s)) return NULL;
+    oracle_prep *pr = (oracle_prep *)calloc(1, sizeof(oracle_prep));
+    if (!pr) return NULL;
+    pr->B = c->B;
+    pr->n_part = (int64_t *)calloc((size_t)c->B, sizeof(int64_t));
+    if (!pr->n_part ||
+        bucket_entries(c, s->row_piece, s->col_piece, s->nnz, s->row, s->col, &pr->order, &pr->beg) ||
+        bucket_entries(c, s->row_piece, s->col_piece, s->nho, s->hrow, s->hcol, &pr->ho_order, &pr->ho_beg)) {
+        oracle_release(pr);
+        return NULL;
+    }
+    for (int32_t p = 0; p < c->B; ++p)
+        pr->n_part[p] = pr->beg[(int64_t)(p + 1) * c->B] - pr->beg[(int64_t)p * c->B];
+    return pr;
+}
+
+/* Threads used by the parallel loops (OpenMP); n < 1 leaves the setting. */
+int oracle_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
 /* Number of training entries in each part, |Pi_p|. */
 int oracle_part_sizes(const oracle_cfg *c, const oracle_state *s, int64_t *n_p)
 {
@@ -306,43 +389,58 @@ int oracle_part_sizes(const oracle_cfg *c, const oracle_state *s, int64_t *n_p)
  * receive the matching absolute-value bound
  *   sum_j (|v| + sum_k' |w_ik' h_k'j|) mu~^(beta-2)/phi |h_kj|   (times the scale),
  * used to scale the rounding tolerance of a single GPU step.
- * Entries are visited in (i,j) lexicographic order with sequential sums. */
-static void part_gradient(const oracle_cfg *c, const oracle_state *s, const int64_t *order,
-                          int64_t beg, int64_t end, double scale, double *gW, double *gH,
-                          double *gpW, double *gpH)
+ * The blocks of the part share no row and no column (Definition 2), so they
+ * are summed independently (one thread per block at a time); inside a block
+ * the entries are visited in (i,j) lexicographic order with sequential sums,
+ * so every sum has the same terms in the same order for any thread count. */
+static void part_gradient(const oracle_cfg *c, const oracle_state *s, const oracle_prep *pr, int32_t p,
+                          double scale, double *gW, double *gH, double *gpW, double *gpH)
 {
     int64_t I = c->I, J = c->J;
-    int32_t K = c->K;
-    memset(gW, 0, sizeof(double) * (size_t)(I * K));
-    memset(gH, 0, sizeof(double) * (size_t)(K * J));
-    if (gpW) memset(gpW, 0, sizeof(double) * (size_t)(I * K));
-    if (gpH) memset(gpH, 0, sizeof(double) * (size_t)(K * J));
-    for (int64_t n = beg; n < end; ++n) {
-        int64_t e = order[n];
-        int64_t i = s->row[e], j = s->col[e];
-        double v = s->val[e];
-        double mu = 0.0, mu_abs = 0.0;
-        for (int32_t k = 0; k < K; ++k) {
-            double prod = model_value(c, s->W[i * K + k]) * model_value(c, s->H[k * J + j]);
-            mu += prod;
-            mu_abs += fabs(prod);
-        }
-        double mu_t = floored_mean(c, mu);
-        double e_ij = residual(c, v, mu_t);
-        double e_abs = (fabs(v) + mu_abs) * pow(mu_t, c->beta - 2.0) / c->phi;
-        for (int32_t k = 0; k < K; ++k) {
-            double w = s->W[i * K + k], h = s->H[k * J + j];
-            gW[i * K + k] += e_ij * model_value(c, h) * model_sign(c, w);
-            gH[k * J + j] += e_ij * model_value(c, w) * model_sign(c, h);
-            if (gpW) gpW[i * K + k] += e_abs * fabs(h);
-            if (gpH) gpH[k * J + j] += e_abs * fabs(w);
+    int32_t K = c->K, B = c->B;
+#pragma omp parallel for schedule(static) if (I * K >= OR_PAR_MIN)
+    for (int64_t m = 0; m < I * K; ++m) {
+        gW[m] = 0.0;
+        if (gpW) gpW[m] = 0.0;
+    }
+#pragma omp parallel for schedule(static) if ((int64_t)K * J >= OR_PAR_MIN)
+    for (int64_t m = 0; m < (int64_t)K * J; ++m) {
+        gH[m] = 0.0;
+        if (gpH) gpH[m] = 0.0;
+    }
+    const int64_t part_work = (pr->beg[(int64_t)(p + 1) * B] - pr->beg[(int64_t)p * B]) * K;
+#pragma omp parallel for schedule(dynamic, 1) if (part_work >= OR_PAR_MIN)
+    for (int32_t b = 0; b < B; ++b) {
+        int64_t beg = pr->beg[(int64_t)p * B + b], end = pr->beg[(int64_t)p * B + b + 1];
+        for (int64_t n = beg; n < end; ++n) {
+            int64_t e = pr->order[n];
+            int64_t i = s->row[e], j = s->col[e];
+            double v = s->val[e];
+            double mu = 0.0, mu_abs = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                double prod = model_value(c, s->W[i * K + k]) * model_value(c, s->H[k * J + j]);
+                mu += prod;
+                mu_abs += fabs(prod);
+            }
+            double mu_t = floored_mean(c, mu);
+            double e_ij = residual(c, v, mu_t);
+            double e_abs = (fabs(v) + mu_abs) * pow(mu_t, c->beta - 2.0) / c->phi;
+            for (int32_t k = 0; k < K; ++k) {
+                double w = s->W[i * K + k], h = s->H[k * J + j];
+                gW[i * K + k] += e_ij * model_value(c, h) * model_sign(c, w);
+                gH[k * J + j] += e_ij * model_value(c, w) * model_sign(c, h);
+                if (gpW) gpW[i * K + k] += e_abs * fabs(h);
+                if (gpH) gpH[k * J + j] += e_abs * fabs(w);
+            }
         }
     }
+#pragma omp parallel for schedule(static) if (I * K >= OR_PAR_MIN)
     for (int64_t m = 0; m < I * K; ++m) {
         gW[m] *= scale;
         if (gpW) gpW[m] *= scale;
     }
-    for (int64_t m = 0; m < K * J; ++m) {
+#pragma omp parallel for schedule(static) if ((int64_t)K * J >= OR_PAR_MIN)
+    for (int64_t m = 0; m < (int64_t)K * J; ++m) {
         gH[m] *= scale;
         if (gpH) gpH[m] *= scale;
     }
@@ -361,14 +459,13 @@ int oracle_drift(const oracle_cfg *c, const oracle_state *s, int32_t p, double *
     int rc = check_inputs(c, s);
     if (rc) return rc;
     if (p < 0 || p >= c->B) return OR_EARG;
-    int64_t *order = NULL, *beg = NULL;
-    rc = bucket_by_part(c, s->row_piece, s->col_piece, s->nnz, s->row, s->col, &order, &beg);
-    if (rc) return rc;
-    double scale = part_scale(s->nnz, beg[p + 1] - beg[p]);
-    part_gradient(c, s, order, beg[p], beg[p + 1], scale, dW, dH, NULL, NULL);
+    oracle_prep *pr = oracle_prepare(c, s);
+    if (!pr) return OR_ENOMEM;
+    double scale = part_scale(s->nnz, pr->n_part[p]);
+    part_gradient(c, s, pr, p, scale, dW, dH, NULL, NULL);
     for (int64_t m = 0; m < c->I * c->K; ++m) dW[m] += prior_grad(c, s->W[m], c->lambda_w);
     for (int64_t m = 0; m < (int64_t)c->K * c->J; ++m) dH[m] += prior_grad(c, s->H[m], c->lambda_h);
-    free(order); free(beg);
+    oracle_release(pr);
     return OR_OK;
 }
 
@@ -422,52 +519,65 @@ int32_t oracle_part_at(const oracle_cfg *c, int64_t t, const int64_t *n_p, int64
     return c->B - 1;
 }
 
-int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bound_W,
-               double *bound_H)
+/* Langevin step of one factor row (W, stride 1 over k) or column (H, stride
+ * J over k): x <- x + eps (g + prior'(x)) + sigma z, then |x| if mirroring,
+ * with z the K normals of that row or column at iteration t.  z and rad are
+ * K-long work arrays of the calling thread. */
+static void step_vector(const oracle_cfg *c, int64_t t, uint32_t stream, int64_t index, double lambda,
+                        double eps, double sigma, double *x, int64_t stride, const double *g, const double *gp,
+                        double *bound, double *z, double *rad)
+{
+    int32_t K = c->K;
+    if (c->flags & OR_FLAG_NOISE_OFF) {
+        for (int32_t k = 0; k < K; ++k) { z[k] = 0.0; rad[k] = 0.0; }
+    } else {
+        oracle_normals(c->seed, t, stream, index, K, z, rad);
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        int64_t m = k * stride;
+        double xo = x[m];
+        double pg = prior_grad(c, xo, lambda);
+        double xn = xo + eps * (g[m] + pg) + sigma * z[k];
+        if (c->mirror) xn = fabs(xn);
+        if (bound) bound[m] = fabs(xo) + eps * (gp[m] + fabs(pg)) + sigma * rad[k];
+        x[m] = xn;
+    }
+}
+
+int oracle_run_prepared(const oracle_cfg *c, oracle_state *s, const oracle_prep *pr, int64_t n_iter,
+                        double *bound_W, double *bound_H)
 {
     int rc = check_inputs(c, s);
     if (rc) return rc;
-    if (c->thin < 1) return OR_EARG;
+    if (c->thin < 1 || !pr || pr->B != c->B) return OR_EARG;
     int64_t I = c->I, J = c->J;
     int32_t K = c->K, B = c->B;
-
-    int64_t *order = NULL, *beg = NULL, *ho_order = NULL, *ho_beg = NULL, *n_part = NULL;
-    rc = bucket_by_part(c, s->row_piece, s->col_piece, s->nnz, s->row, s->col, &order, &beg);
-    if (rc) return rc;
-    rc = bucket_by_part(c, s->row_piece, s->col_piece, s->nho, s->hrow, s->hcol, &ho_order, &ho_beg);
-    if (rc) { free(order); free(beg); return rc; }
 
     double *gW = (double *)malloc(sizeof(double) * (size_t)(I * K));
     double *gH = (double *)malloc(sizeof(double) * (size_t)(K * J));
     double *gpW = bound_W ? (double *)malloc(sizeof(double) * (size_t)(I * K)) : NULL;
     double *gpH = bound_H ? (double *)malloc(sizeof(double) * (size_t)(K * J)) : NULL;
-    double *z = (double *)malloc(sizeof(double) * (size_t)K);
-    double *rad = (double *)malloc(sizeof(double) * (size_t)K);
-    if (!gW || !gH || !z || !rad || (bound_W && !gpW) || (bound_H && !gpH)) {
+    if (!gW || !gH || (bound_W && !gpW) || (bound_H && !gpH)) {
         rc = OR_ENOMEM;
         goto done;
     }
-
-    n_part = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);
-    if (!n_part) {
-        rc = OR_ENOMEM;
-        goto done;
-    }
-    for (int32_t q = 0; q < B; ++q) n_part[q] = beg[q + 1] - beg[q];
 
     for (int64_t it = 0; it < n_iter; ++it) {
         int64_t t = s->t;
         /* Set the step size; pick the part. */
         double eps = oracle_eps(c, t);
         double sigma = sqrt(2.0 * eps);
-        int32_t p = oracle_part_at(c, t, n_part, s->nnz);
-        double scale = part_scale(s->nnz, beg[p + 1] - beg[p]);
+        int32_t p = oracle_part_at(c, t, pr->n_part, s->nnz);
+        double scale = part_scale(s->nnz, pr->n_part[p]);
         int last = (it == n_iter - 1);
 
-        /* Held-out predictive sums use the state before this update. */
+        /* Held-out predictive sums use the state before this update; every
+         * cell has its own sum. */
         if (t >= c->burn_in) {
-            for (int64_t n = ho_beg[p]; n < ho_beg[p + 1]; ++n) {
-                int64_t e = ho_order[n];
+            int64_t h0 = pr->ho_beg[(int64_t)p * B], h1 = pr->ho_beg[(int64_t)(p + 1) * B];
+#pragma omp parallel for schedule(static) if ((h1 - h0) * K >= OR_PAR_MIN)
+            for (int64_t n = h0; n < h1; ++n) {
+                int64_t e = pr->ho_order[n];
                 int64_t i = s->hrow[e], j = s->hcol[e];
                 double mu = 0.0;
                 for (int32_t k = 0; k < K; ++k)
@@ -478,58 +588,64 @@ int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bou
         }
 
         /* Likelihood gradient over the part, at the old state (Eq. 8-9). */
-        part_gradient(c, s, order, beg[p], beg[p + 1], scale, gW, gH, last ? gpW : NULL,
-                      last ? gpH : NULL);
+        part_gradient(c, s, pr, p, scale, gW, gH, last ? gpW : NULL, last ? gpH : NULL);
 
         /* Every row of W and every column of H lies in exactly one block of
-         * the part (Definition 2), so the update sweeps all of W and H. */
+         * the part (Definition 2), so the update sweeps all of W and H; each
+         * row and column is stepped independently. */
         if (!(c->flags & OR_FLAG_FREEZE_W)) {
-            for (int64_t i = 0; i < I; ++i) {
-                if (c->flags & OR_FLAG_NOISE_OFF) {
-                    for (int32_t k = 0; k < K; ++k) { z[k] = 0.0; rad[k] = 0.0; }
-                } else {
-                    oracle_normals(c->seed, t, OR_STREAM_W, i, K, z, rad);
+#pragma omp parallel if (I * K >= OR_PAR_MIN / 8)
+            {
+                double *z = (double *)malloc(sizeof(double) * (size_t)K);
+                double *rad = (double *)malloc(sizeof(double) * (size_t)K);
+#pragma omp for schedule(static)
+                for (int64_t i = 0; i < I; ++i)
+                    if (z && rad)
+                        step_vector(c, t, OR_STREAM_W, i, c->lambda_w, eps, sigma, s->W + i * K, 1, gW + i * K,
+                                    (last && bound_W) ? gpW + i * K : NULL, (last && bound_W) ? bound_W + i * K : NULL,
+                                    z, rad);
+                if (!z || !rad) {
+#pragma omp atomic write
+                    rc = OR_ENOMEM;
                 }
-                for (int32_t k = 0; k < K; ++k) {
-                    double x = s->W[i * K + k];
-                    double pg = prior_grad(c, x, c->lambda_w);
-                    double xn = x + eps * (gW[i * K + k] + pg) + sigma * z[k];
-                    if (c->mirror) xn = fabs(xn);
-                    if (last && bound_W)
-                        bound_W[i * K + k] = fabs(x) + eps * (gpW[i * K + k] + fabs(pg)) + sigma * rad[k];
-                    s->W[i * K + k] = xn;
-                }
+                free(z);
+                free(rad);
             }
+            if (rc) goto done;
         } else if (last && bound_W) {
             for (int64_t m = 0; m < I * K; ++m) bound_W[m] = fabs(s->W[m]);
         }
         if (!(c->flags & OR_FLAG_FREEZE_H)) {
-            for (int64_t j = 0; j < J; ++j) {
-                if (c->flags & OR_FLAG_NOISE_OFF) {
-                    for (int32_t k = 0; k < K; ++k) { z[k] = 0.0; rad[k] = 0.0; }
-                } else {
-                    oracle_normals(c->seed, t, OR_STREAM_H, j, K, z, rad);
+#pragma omp parallel if ((int64_t)K * J >= OR_PAR_MIN / 8)
+            {
+                double *z = (double *)malloc(sizeof(double) * (size_t)K);
+                double *rad = (double *)malloc(sizeof(double) * (size_t)K);
+#pragma omp for schedule(static)
+                for (int64_t j = 0; j < J; ++j)
+                    if (z && rad)
+                        step_vector(c, t, OR_STREAM_H, j, c->lambda_h, eps, sigma, s->H + j, J, gH + j,
+                                    (last && bound_H) ? gpH + j : NULL, (last && bound_H) ? bound_H + j : NULL,
+                                    z, rad);
+                if (!z || !rad) {
+#pragma omp atomic write
+                    rc = OR_ENOMEM;
                 }
-                for (int32_t k = 0; k < K; ++k) {
-                    double x = s->H[k * J + j];
-                    double pg = prior_grad(c, x, c->lambda_h);
-                    double xn = x + eps * (gH[k * J + j] + pg) + sigma * z[k];
-                    if (c->mirror) xn = fabs(xn);
-                    if (last && bound_H)
-                        bound_H[k * J + j] = fabs(x) + eps * (gpH[k * J + j] + fabs(pg)) + sigma * rad[k];
-                    s->H[k * J + j] = xn;
-                }
+                free(z);
+                free(rad);
             }
+            if (rc) goto done;
         } else if (last && bound_H) {
             for (int64_t m = 0; m < (int64_t)K * J; ++m) bound_H[m] = fabs(s->H[m]);
         }
 
         /* Monte Carlo sums of the new sample at kept iterations. */
         if (t >= c->burn_in && (t - c->burn_in) % c->thin == 0) {
+#pragma omp parallel for schedule(static) if (I * K >= OR_PAR_MIN)
             for (int64_t m = 0; m < I * K; ++m) {
                 s->sumW[m] += s->W[m];
                 s->sumW2[m] += s->W[m] * s->W[m];
             }
+#pragma omp parallel for schedule(static) if ((int64_t)K * J >= OR_PAR_MIN)
             for (int64_t m = 0; m < (int64_t)K * J; ++m) {
                 s->sumH[m] += s->H[m];
                 s->sumH2[m] += s->H[m] * s->H[m];
@@ -538,14 +654,27 @@ int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bou
         }
         s->t = t + 1;
 
-        for (int64_t m = 0; m < I * K; ++m)
-            if (!isfinite(s->W[m])) { rc = OR_ENUMERIC; goto done; }
-        for (int64_t m = 0; m < (int64_t)K * J; ++m)
-            if (!isfinite(s->H[m])) { rc = OR_ENUMERIC; goto done; }
+        int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad) if (I * K >= OR_PAR_MIN)
+        for (int64_t m = 0; m < I * K; ++m) bad = bad || !isfinite(s->W[m]);
+#pragma omp parallel for schedule(static) reduction(|| : bad) if ((int64_t)K * J >= OR_PAR_MIN)
+        for (int64_t m = 0; m < (int64_t)K * J; ++m) bad = bad || !isfinite(s->H[m]);
+        if (bad) { rc = OR_ENUMERIC; goto done; }
     }
 
 done:
-    free(gW); free(gH); free(gpW); free(gpH); free(z); free(rad);
-    free(order); free(beg); free(ho_order); free(ho_beg); free(n_part);
+    free(gW); free(gH); free(gpW); free(gpH);
+    return rc;
+}
+
+/* One-shot form: buckets the data, runs, and frees the buckets. */
+int oracle_run(const oracle_cfg *c, oracle_state *s, int64_t n_iter, double *bound_W, double *bound_H)
+{
+    int rc = check_inputs(c, s);
+    if (rc) return rc;
+    oracle_prep *pr = oracle_prepare(c, s);
+    if (!pr) return OR_ENOMEM;
+    rc = oracle_run_prepared(c, s, pr, n_iter, bound_W, bound_H);
+    oracle_release(pr);
     return rc;
 }
