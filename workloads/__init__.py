@@ -371,3 +371,38 @@ def job_arrivals(n_jobs, rate=20.0, seed=3005):
     if rate <= 0:
         return np.zeros(n_jobs)
     return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, n_jobs))
+
+
+# ------------------------------------------------------------- named configs
+def by_name(name):
+    """The named workloads the benchmark, the long-run parity tests and the
+    stored oracle results share (moments kept every 10th post-burn-in
+    iteration where the run is 1000 iterations long)."""
+    if name == "dense_poisson_256":
+        return dense_poisson()
+    if name == "sparse_ratings_70k":
+        wl = sparse_ratings()
+    elif name == "dense_tweedie_1025x100k":
+        wl = dense_tweedie()
+    elif name == "sparse_ratings_480k":
+        wl = sparse_ratings(I=480_000, J=17_800, nnz=100_000_000, K_true=30, K=100, B=64, zipf_a=1.1,
+                            data_seed=1004, chain_seed=2004, name=name)
+    elif name == "sparse_ratings_small":
+        wl = sparse_ratings(I=7000, J=1070, nnz=1_000_000, B=32, name=name)
+    elif name == "paper_poisson_1024":
+        # the paper's synthetic Poisson NMF, fully observed.  Its step size
+        # (0.01 / t)^0.51 diverges within a few iterations under this
+        # gradient scaling (N / |part| times the part's sum), so the step
+        # constant comes from the stability rule with the paper's decay
+        wl = dense_poisson(I=1024, J=1024, K=32, B=32, heldout=0.0, data_seed=1010, chain_seed=2010,
+                           T=10_000, burn_in=5_000, thin=10, name=name)
+        wl.eps_a = step_scale(wl.row, wl.col, wl.val, wl.I, wl.J, wl.beta, wl.phi)
+        return wl
+    elif name == "paper_spectrum_256":
+        return dense_poisson(I=256, J=256, K=8, B=8, heldout=0.0, data_seed=1011, chain_seed=2011,
+                             T=10_000, burn_in=5_000, thin=10, eps_a=1e-3, eps_t0=1.0, eps_gamma=0.51, name=name)
+    else:
+        raise KeyError(f"unknown workload {name}")
+    wl.thin = 10
+    return wl
+
