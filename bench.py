@@ -1,8 +1,9 @@
 """Benchmark: observed-entry SGLD updates/s of the PSGLD sampler on one MI355X.
 
-Workload (default): recommender-shaped sparse Gaussian MF, I = 70,000 rows,
-J = 10,700 columns, 10M observed ratings (9M training, 1M held out), fit
-K = 50, B = 32, T = 1000 iterations with burn-in 500 and moments kept every
+Workload (default): the large recommender-shaped sparse Gaussian MF,
+I = 480,000 rows, J = 17,800 columns, 100M observed ratings (90M training,
+10M held out), Zipf(1.1) column popularity and lognormal row activity, fit
+K = 100, B = 64, T = 1000 iterations with burn-in 500 and moments kept every
 10th post-burn-in iteration.  A step is one PSGLD iteration (one part).
 
 The timed region is one psgld_step call of K iterations from t = 0 (the
@@ -12,8 +13,12 @@ kernel's average launch duration is the same events' elapsed time over the
 iterations (one launch each, back to back); the roofline fraction divides the
 mean algorithmic bytes of those iterations by it.  A second pass replays the
 same iterations with HIP events around every launch, for the averages before
-and after burn-in.  The FP64 oracle is timed on the host on a bounded sample
-(cpu_baseline).
+and after burn-in.  A third pass runs the workload's whole chain (T
+iterations from t = 0, moments and held-out sums after burn-in) and reports
+its held-out RMSE beside the FP64 oracle's stored full run, so the rate is
+quoted at a held-out RMSE matched to the oracle's.  The FP64 oracle is timed
+on the host's cores on a bounded sample (cpu_baseline), with all threads and
+with one.
 
 Prints one JSON line.
 """
@@ -164,62 +169,61 @@ def measured_traffic(key, kind):
     return 1024.0 * (run["FETCH_SIZE_KiB"] * ref["fetch_scale"] + run["WRITE_SIZE_KiB"] * ref["write_scale"])
 
 
+def stored_oracle_rmse(wl):
+    """The FP64 oracle's held-out RMSE after the same whole run, as stored in
+    tests/golden/heldout_rmse.json (written from the oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "heldout_rmse.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f).get(wl.name)
+    if not ref or (ref["T"], ref["burn_in"], ref["thin"], ref["n_heldout"]) != (wl.T, wl.burn_in, wl.thin,
+                                                                                 len(wl.hval)):
+        return None
+    return ref["heldout_rmse"]
+
+
 def make_workload(name):
-    if name == "dense_tweedie_1025x100k":
-        wl = workloads.dense_tweedie()
-        wl.thin = 10
-        return wl
-    if name == "sparse_ratings_70k":
-        wl = workloads.sparse_ratings()
-        wl.thin = 10
-        return wl
-    if name == "sparse_ratings_480k":
-        wl = workloads.sparse_ratings(I=480_000, J=17_800, nnz=100_000_000, K_true=30, K=100, B=64,
-                                      zipf_a=1.1, data_seed=1004, chain_seed=2004, name=name)
-        wl.thin = 10
-        return wl
-    if name == "paper_poisson_1024":
-        # the paper's synthetic Poisson NMF, fully observed.  Its step size
-        # (0.01 / t)^0.51 diverges within a few iterations under this
-        # gradient scaling (N / |part| times the part's sum), so the step
-        # constant comes from the stability rule with the paper's decay
-        wl = workloads.dense_poisson(I=1024, J=1024, K=32, B=32, heldout=0.0, data_seed=1010,
-                                     chain_seed=2010, T=10_000, burn_in=5_000, thin=10, name=name)
-        wl.eps_a = workloads.step_scale(wl.row, wl.col, wl.val, wl.I, wl.J, wl.beta, wl.phi)
-        return wl
-    if name == "paper_spectrum_256":
-        return workloads.dense_poisson(I=256, J=256, K=8, B=8, heldout=0.0, data_seed=1011,
-                                       chain_seed=2011, T=10_000, burn_in=5_000, thin=10,
-                                       eps_a=1e-3, eps_t0=1.0, eps_gamma=0.51, name=name)
-    if name == "dense_poisson_256":
-        return workloads.dense_poisson()
-    if name == "sparse_ratings_small":
-        wl = workloads.sparse_ratings(I=7000, J=1070, nnz=1_000_000, B=32, name=name)
-        wl.thin = 10
-        return wl
-    raise SystemExit(f"unknown workload {name}")
+    try:
+        return workloads.by_name(name)
+    except KeyError as e:
+        raise SystemExit(str(e))
 
 
-def cpu_baseline(wl, seconds, part_order="cyclic", row_piece=None, col_piece=None, iters=0):
-    """The oracle on the host: whole cycles of the B parts from t = 0 until
-    `seconds` of oracle time have passed (or exactly `iters` iterations)."""
+def cpu_baseline(wl, seconds, part_order="cyclic", row_piece=None, col_piece=None, iters=0, single_iters=1):
+    """The oracle on the host: iterations from t = 0 with all its threads
+    until `seconds` of oracle time have passed (at least two iterations, or
+    exactly `iters`), then `single_iters` more on one thread.  Bucketing the
+    entries (once per chain) is not timed."""
     import oracle
+    threads = oracle.threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
     cfg = oracle.Config(**wl.fit_kwargs())
     cfg.part_order = part_order
     ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol,
                       row_piece=row_piece, col_piece=col_piece)
     n_p = ch.part_sizes()
-    done, dt = 0, 0.0
-    while (done < iters) if iters > 0 else (dt < seconds):
-        n = min(wl.B, iters - done) if iters > 0 else wl.B
-        t0 = time.perf_counter()
-        ch.run(n)
-        dt += time.perf_counter() - t0
-        done += n
-    entries = int(sum(n_p[ch.part_at(t)] for t in range(done)))
-    return {"value": entries / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} iterations from t=0 ({done / wl.B:g} cycles of the {wl.B} parts) "
-                      f"of the same workload, single-threaded FP64 C, {dt:.1f} s of oracle time"}
+    ch._prepared()
+
+    def timed(n_max, budget):
+        done, dt, ent = 0, 0.0, 0
+        while done < n_max and (done < 2 or dt < budget):
+            t = ch.t
+            t0 = time.perf_counter()
+            ch.run(1)
+            dt += time.perf_counter() - t0
+            ent += int(n_p[ch.part_at(t)])
+            done += 1
+        return done, dt, ent
+
+    done, dt, ent = timed(iters if iters > 0 else 10 ** 9, seconds if iters <= 0 else float("inf"))
+    oracle.threads(1)
+    d1, dt1, ent1 = timed(max(single_iters, 1), 0.0)
+    oracle.threads(threads)
+    return {"value": ent / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": ent1 / dt1,
+            "sample": f"{done} iterations from t=0 of the same workload on {threads} threads "
+                      f"({dt:.1f} s of oracle time), then {d1} on one thread ({dt1:.1f} s); FP64 C, "
+                      f"threads over the blocks of a part and the rows/columns of the update"}
 
 
 def serve_main(args):
@@ -303,9 +307,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sparse_ratings_70k")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="oracle time for the CPU baseline (whole cycles of the parts)")
+    ap.add_argument("--workload", default="sparse_ratings_480k")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="oracle time on all threads for the CPU baseline")
+    ap.add_argument("--cpu-single-iters", type=int, default=1,
+                    help="oracle iterations on one thread for the CPU baseline")
+    ap.add_argument("--no-full-chain", action="store_true",
+                    help="skip the whole-chain pass (held-out RMSE after T iterations)")
     ap.add_argument("--cpu-iters", type=int, default=0, help="exact oracle iterations instead (0: by time)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
@@ -452,13 +460,37 @@ def main():
     print(f"[bench] pass 2: iteration avg {float(durs.mean()) * 1e3:.2f} us with events around each launch; "
           f"timed region {avg_ms * 1e3:.2f} us per iteration, roofline {roof['achieved']:.1f} "
           f"{roof['unit']} ({roof['bound']}), RMSE {rmse2}", file=sys.stderr, flush=True)
+
+    # pass 3: the whole chain (T iterations from t = 0, moments and held-out
+    # sums after burn-in), whose held-out RMSE is compared with the oracle's
+    chain = None
+    if not args.no_full_chain and len(wl.hrow) and wl.T > wl.burn_in:
+        s.set_state(state0)
+        ev.sync()
+        e2, e3 = ev.create(2)
+        ev.record(e2, stream)
+        s.step(wl.T, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        ev.record(e3, stream)
+        chain_ms = ev.elapsed_ms(e2, e3)
+        s.sync()
+        chain_rmse = s.heldout_rmse()
+        chain_entries = int(sum(n_p[s.part_at(t)] for t in range(wl.T)))
+        ref = stored_oracle_rmse(wl)
+        chain = {"T": wl.T, "burn_in": wl.burn_in, "thin": wl.thin, "ms": chain_ms,
+                 "updates_per_s": chain_entries / (chain_ms * 1e-3), "heldout_rmse": chain_rmse,
+                 "oracle_heldout_rmse": ref,
+                 "rmse_rel_diff": None if ref is None else abs(chain_rmse - ref) / ref}
+        print(f"[bench] pass 3: whole chain of {wl.T} iterations in {chain_ms:.2f} ms "
+              f"({chain['updates_per_s']:.4g} updates/s), held-out RMSE {chain_rmse:.6f}"
+              f" (oracle {ref})", file=sys.stderr, flush=True)
     s.close()
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds, args.part_order, pieces.get("row_piece"), pieces.get("col_piece"),
-                           iters=args.cpu_iters)
-        print(f"[bench] oracle: {cpu['value']:.4g} updates/s", file=sys.stderr, flush=True)
+                           iters=args.cpu_iters, single_iters=args.cpu_single_iters)
+        print(f"[bench] oracle: {cpu['value']:.4g} updates/s on {cpu['cores']} threads, "
+              f"{cpu['single_thread_value']:.4g} on one", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
@@ -469,8 +501,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,
-                   "T": args.steps, "burn_in": wl.burn_in, "thin": wl.thin,
-                   "heldout_rmse": rmse, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": runs_dense,
+                   "timed_iterations": args.steps, "T": wl.T, "burn_in": wl.burn_in, "thin": wl.thin,
+                   "heldout_rmse": chain["heldout_rmse"] if chain else rmse,
+                   "oracle_heldout_rmse": chain["oracle_heldout_rmse"] if chain else None,
+                   "whole_chain": chain, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": runs_dense,
                    "dense_blocks": int(placed.sum()),
                    "precision": args.precision if runs_dense else "f32", "parallelism": "single-gpu",
                    "part_order": args.part_order, "balanced_pieces": bool(pieces),

@@ -29,7 +29,8 @@
  *    Output arrays are caller-allocated with the sizes stated below.
  *  - W is exchanged as I x K row-major and H as K x J row-major (the paper's
  *    orientation), in the precision named in each signature.
- *  - The library owns the context and all device memory it allocates.
+ *  - The library owns the context and all device memory it allocates,
+ *    through the caller's allocator hooks when options give them.
  *  - A context is used by one host thread at a time.  Stepping is
  *    asynchronous on the context's stream; getters synchronise it.
  */
@@ -125,12 +126,31 @@ typedef struct {
                                  even when dense (default 256: one dense
                                  work-group's width; narrower tiles measured
                                  slower than the coordinate kernel) */
+    int32_t persistent_grid;  /* work-groups of a persistent launch; 0 = as many
+                                 as the device holds at once (capped by the
+                                 work).  Fewer make each work-group run several
+                                 tasks of an iteration in turn. */
+    /* Device memory of the context (Algorithm 1's inputs and outputs held on
+     * the GPU: factors, entries, moment sums, schedules, scratch).  With both
+     * hooks NULL the library calls hipMalloc / hipFree itself; with both set
+     * every device allocation of the context goes through them instead (the
+     * Python binding passes PyTorch's caching allocator), so the caller sees
+     * and accounts for all of it.  dev_alloc(bytes, alloc_user) returns device
+     * memory of options.device aligned to 256 bytes, or NULL (the calling
+     * function then fails with PSGLD_E_NOMEM); it is called with that device
+     * current, on the host thread that called the library.  dev_free(ptr,
+     * bytes, alloc_user) returns a block with the size it was asked for; the
+     * library calls it only once the context's stream has finished every
+     * use of the block.  Setting only one hook is PSGLD_E_ARG. */
+    void *(*dev_alloc)(size_t bytes, void *user);
+    void (*dev_free)(void *ptr, size_t bytes, void *user);
+    void *alloc_user;
 } psgld_options;
 
 /* Fills *opt with the defaults: seed 0, burn_in 0, thin 1, FP32,
  * dense_threshold 0.3, mu_floor 1e-6, contiguous pieces, own stream,
  * no test flags, device 0, graph_iters -1, persistent 0, cyclic part order,
- * dense_min_cols 256. */
+ * dense_min_cols 256, persistent_grid 0, no allocator hooks (hipMalloc). */
 void psgld_default_options(psgld_options *opt);
 
 /* Creates a context for an I x J matrix, rank K (1..256), B x B blocks
@@ -328,6 +348,11 @@ typedef struct {
     int32_t iters_per_tick;   /* iterations per job per tick; >= 1 */
     int32_t device;           /* HIP device ordinal */
     int32_t persistent;       /* 1: a tick runs in cooperative launches (options.persistent of the jobs) */
+    /* Allocator hooks handed to every job's context (as in psgld_options);
+     * a job's device bytes are what its context asked of them. */
+    void *(*dev_alloc)(size_t bytes, void *user);
+    void (*dev_free)(void *ptr, size_t bytes, void *user);
+    void *alloc_user;
 } psgld_server_options;
 
 /* One complete run.  Data as for psgld_load_coo (row != NULL) or

@@ -56,18 +56,68 @@ class psgld_eps_schedule(C.Structure):
     _fields_ = [("a", C.c_double), ("t0", C.c_double), ("gamma", C.c_double)]
 
 
+# allocator hooks of psgld_options: void *dev_alloc(size_t, void *), void dev_free(void *, size_t, void *)
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
 class psgld_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("burn_in", C.c_int64), ("thin", C.c_int32),
                 ("precision", C.c_int32), ("dense_threshold", C.c_double),
                 ("mu_floor", C.c_double), ("row_piece", C.c_void_p), ("col_piece", C.c_void_p),
                 ("stream", C.c_void_p), ("test_flags", C.c_uint32), ("device", C.c_int32),
                 ("graph_iters", C.c_int32), ("persistent", C.c_int32), ("part_order", C.c_int32),
-                ("dense_min_cols", C.c_int32)]
+                ("dense_min_cols", C.c_int32), ("persistent_grid", C.c_int32),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", C.c_void_p)]
 
 
 class psgld_server_options(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("iters_per_tick", C.c_int32),
-                ("device", C.c_int32), ("persistent", C.c_int32)]
+                ("device", C.c_int32), ("persistent", C.c_int32),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """The allocator hooks of psgld_options backed by PyTorch's caching
+    allocator on `device`, with blocks tied to `stream` (a hipStream_t handle,
+    0 = the device's default stream).  Keep the object alive as long as any
+    context created with its hooks.  Counts the bytes it holds."""
+
+    def __init__(self, device=0, stream=0, fail_after=None):
+        import torch
+        self._torch = torch
+        self.device = int(device)
+        self.stream = int(stream or 0)
+        self.held = {}              # ptr -> bytes
+        self.calls = 0
+        self.fail_after = fail_after   # test hook: return NULL from this call on
+        self.alloc_fn = DEV_ALLOC_FN(self._alloc)
+        self.free_fn = DEV_FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        self.calls += 1
+        if self.fail_after is not None and self.calls > self.fail_after:
+            return None
+        try:
+            p = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:
+            return None
+        self.held[p] = int(nbytes)
+        return p
+
+    def _free(self, ptr, nbytes, user):
+        if ptr in self.held:
+            del self.held[ptr]
+            self._torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def bytes(self):
+        return sum(self.held.values())
+
+    def install(self, opt):
+        opt.dev_alloc = self.alloc_fn
+        opt.dev_free = self.free_fn
+        opt.alloc_user = None
 
 
 class psgld_job(C.Structure):
@@ -368,7 +418,12 @@ class PSGLD:
                  lambda_h=1.0, mirror=False, seed=0, burn_in=0, thin=1, precision=PSGLD_FP32,
                  dense_threshold=0.3, mu_floor=1e-6, row_piece=None, col_piece=None,
                  stream: Optional[int] = None, test_flags=0, device=0, graph_iters=-1, persistent=0,
-                 part_order="cyclic", dense_min_cols=256):
+                 part_order="cyclic", dense_min_cols=256, persistent_grid=0, allocator=None):
+        """allocator: None (the library's hipMalloc) or an object with an
+        install(opt) method setting the hooks, e.g. TorchAllocator; the
+        string "torch" makes a TorchAllocator on `device` tied to `stream`,
+        or to PyTorch's current stream when no stream is given (then the
+        context also runs on that stream, unless it is the default stream)."""
         self.I, self.J, self.K, self.B = int(I), int(J), int(K), int(B)
         lik = psgld_likelihood(beta, phi)
         pr = psgld_prior(PSGLD_PRIOR_EXPONENTIAL if prior == "exponential" else PSGLD_PRIOR_GAUSSIAN,
@@ -384,6 +439,17 @@ class PSGLD:
         opt.persistent = int(bool(persistent))
         opt.part_order = {"cyclic": PSGLD_PART_CYCLIC, "random": PSGLD_PART_RANDOM}[part_order]
         opt.dense_min_cols = int(dense_min_cols)
+        opt.persistent_grid = int(persistent_grid)
+        if allocator == "torch":
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device).cuda_stream
+                opt.stream = stream or None
+            allocator = TorchAllocator(device, stream or 0)
+        self.allocator = allocator
+        if allocator is not None:
+            allocator.install(opt)
+        self.ctx = None
         self.ctx = psgld_create(self.I, self.J, self.K, self.B, lik, pr, opt)
         self.n_heldout = 0
 
@@ -553,9 +619,12 @@ class Server:
     """Serving loop (psgld_server_*): jobs admitted FIFO under an HBM budget
     and stepped together, iters_per_tick iterations per tick."""
 
-    def __init__(self, hbm_budget, max_active=64, iters_per_tick=25, device=0, persistent=False):
+    def __init__(self, hbm_budget, max_active=64, iters_per_tick=25, device=0, persistent=False, allocator=None):
         opt = psgld_server_options(int(hbm_budget), int(max_active), int(iters_per_tick), int(device),
                                    int(bool(persistent)))
+        self.allocator = TorchAllocator(device) if allocator == "torch" else allocator
+        if self.allocator is not None:
+            self.allocator.install(opt)
         out = C.c_void_p()
         st = lib().psgld_server_create(C.byref(opt), C.byref(out))
         if st != PSGLD_OK:

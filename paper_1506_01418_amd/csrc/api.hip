@@ -76,7 +76,7 @@ struct psgld_ctx {
     std::vector<int64_t> n_p;
     std::vector<int64_t> task_off, n_tasks;
 
-    std::vector<void *> allocs;
+    std::map<void *, size_t> allocs;   // device blocks of the context and their sizes
     int64_t bytes = 0;
     float *W[2] = {nullptr, nullptr}, *H[2] = {nullptr, nullptr};
     int cur = 0;
@@ -168,16 +168,33 @@ hipError_t psgld::use_device(int dev)
 
 namespace {
 
+// Returns one device block of the context to where it came from: the
+// caller's dev_free hook, or hipFree.
+void release_block(const psgld_ctx *c, void *p, size_t bytes)
+{
+    if (c->opt.dev_free) c->opt.dev_free(p, bytes, c->opt.alloc_user);
+    else (void)hipFree(p);
+}
+
+// Every device allocation of a context: through the caller's hooks when
+// the options give them, else hipMalloc.  Sizes are recorded per block.
 template <typename T>
 psgld_status dev_alloc(psgld_ctx *c, T **p, size_t count)
 {
     void *q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    if (hipMalloc(&q, bytes) != hipSuccess) {
+    if (c->opt.dev_alloc) {
+        q = c->opt.dev_alloc(bytes, c->opt.alloc_user);
+        if (!q) return c->fail(PSGLD_E_NOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+        if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+            c->opt.dev_free(q, bytes, c->opt.alloc_user);
+            return c->fail(PSGLD_E_ARG, "allocator hook returned memory not aligned to 256 bytes");
+        }
+    } else if (hipMalloc(&q, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return c->fail(PSGLD_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
-    c->allocs.push_back(q);
+    c->allocs.emplace(q, bytes);
     c->bytes += static_cast<int64_t>(bytes);
     *p = static_cast<T *>(q);
     return PSGLD_OK;
@@ -186,13 +203,12 @@ psgld_status dev_alloc(psgld_ctx *c, T **p, size_t count)
 void dev_free(psgld_ctx *c, void *p)
 {
     if (!p) return;
-    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    auto it = c->allocs.find(p);
     if (it == c->allocs.end()) return;
+    const size_t bytes = it->second;
     c->allocs.erase(it);
-    size_t bytes = 0;
-    (void)hipMemPtrGetInfo(p, &bytes);
     c->bytes -= static_cast<int64_t>(bytes);
-    (void)hipFree(p);
+    release_block(c, p, bytes);
 }
 
 // Destroys every captured graph (after the work already enqueued has run).
@@ -221,9 +237,18 @@ psgld_status ensure_device(psgld_ctx *c)
         c->own_stream = true;
     }
     psgld_status s = dev_alloc(c, &c->nonfinite, 1);
-    if (s) return s;
-    if ((s = dev_alloc(c, &c->clock, 1))) return s;
-    if ((s = dev_alloc(c, &c->barrier, 1))) return s;
+    if (!s) s = dev_alloc(c, &c->clock, 1);
+    if (!s) s = dev_alloc(c, &c->barrier, 1);
+    if (s) {
+        // nothing else exists yet: return what was allocated and the stream
+        for (auto &blk : c->allocs) release_block(c, blk.first, blk.second);
+        c->allocs.clear();
+        c->bytes = 0;
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        c->stream = nullptr;
+        c->own_stream = false;
+        return s;
+    }
     const int32_t big = INT_MAX;
     HIPTRY(c, hipMemcpy(c->nonfinite, &big, sizeof(big), hipMemcpyHostToDevice));
     c->device_ready = true;
@@ -819,7 +844,8 @@ psgld_status step_persistent(psgld_ctx *const *ctxs, int n, int64_t n_iter, hipS
         }
         for (int64_t done = 0; done < n_iter; done += kPersistentIters) {
             const int chunk = static_cast<int>(std::min(kPersistentIters, n_iter - done));
-            HIPTRY(c0, launch_sparse_persistent(b, chunk, c0->lik_kind, c0->lpg, c0->qpl, 0, c0->barrier, stream));
+            HIPTRY(c0, launch_sparse_persistent(b, chunk, c0->lik_kind, c0->lpg, c0->qpl, c0->opt.persistent_grid,
+                                                c0->barrier, stream));
             const std::vector<int32_t> delta(clocks.size(), chunk);
             HIPTRY(c0, launch_advance_clocks(clocks.data(), delta.data(), cnt, stream));
         }
@@ -867,6 +893,10 @@ void psgld_default_options(psgld_options *opt)
     opt->persistent = 0;
     opt->part_order = PSGLD_PART_CYCLIC;
     opt->dense_min_cols = 256;
+    opt->persistent_grid = 0;
+    opt->dev_alloc = nullptr;
+    opt->dev_free = nullptr;
+    opt->alloc_user = nullptr;
 }
 
 psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgld_likelihood *lik,
@@ -898,6 +928,8 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (o.device < 0) return bad("device must be >= 0");
     if (o.part_order != PSGLD_PART_CYCLIC && o.part_order != PSGLD_PART_RANDOM) return bad("unknown part order");
     if (o.dense_min_cols < 1) return bad("dense_min_cols must be >= 1");
+    if (o.persistent_grid < 0) return bad("persistent_grid must be >= 0");
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) return bad("dev_alloc and dev_free go together");
 
     psgld_ctx *c = new (std::nothrow) psgld_ctx();
     if (!c) {
@@ -1289,6 +1321,7 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     }
     return PSGLD_OK;
 }
+
 
 namespace {
 
@@ -1783,7 +1816,7 @@ void psgld_destroy(psgld_ctx *c)
         (void)use_device(c->opt.device);
         (void)hipStreamSynchronize(c->stream);
         drop_graphs(c);
-        for (void *p : c->allocs) (void)hipFree(p);
+        for (auto &blk : c->allocs) release_block(c, blk.first, blk.second);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }

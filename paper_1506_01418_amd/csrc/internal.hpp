@@ -50,12 +50,13 @@ struct HeldEntry {
 // scratch slots split_first .. split_first + n_split - 1 and the last share
 // to finish combines them in slot order and applies the update.
 struct WgTask {
-    int32_t side;
-    int32_t glog2;
+    int16_t side;
+    int16_t glog2;
     int32_t split_first;
-    int16_t split_idx;
-    int16_t n_split;
+    int32_t split_idx;   // 32-bit: an item of up to 2^31 entries may be cut into that many shares
+    int32_t n_split;
 };
+static_assert(sizeof(WgTask) == 16, "a work-group task is 16 bytes");
 
 // One group's item (-1 = none) and its range of entries [s0, s1).
 struct GroupRec {

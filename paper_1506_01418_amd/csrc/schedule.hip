@@ -95,7 +95,8 @@ void build_part_schedule(const int32_t *pre_r, const int32_t *pre_c, int64_t I, 
                     for (int64_t s = 0; s < ns; ++s) {
                         const int64_t a0 = beg + n * s / ns, a1 = beg + n * (s + 1) / ns;
                         Staged st;
-                        st.task = WgTask{side, qlog, first, static_cast<int16_t>(s), static_cast<int16_t>(ns)};
+                        st.task = WgTask{static_cast<int16_t>(side), static_cast<int16_t>(qlog), first, static_cast<int32_t>(s),
+                                          static_cast<int32_t>(ns)};
                         st.recs.resize(Q);
                         for (int g = 0; g < Q; ++g)
                             st.recs[g] = GroupRec{it, static_cast<int32_t>(a0 + (a1 - a0) * g / Q),
@@ -119,7 +120,7 @@ void build_part_schedule(const int32_t *pre_r, const int32_t *pre_c, int64_t I, 
                 const int gl = static_cast<int>(light[pos].first >> 32);
                 const int G = 1 << gl, per = Q / G;
                 Staged st;
-                st.task = WgTask{side, gl, -1, 0, 0};
+                st.task = WgTask{static_cast<int16_t>(side), static_cast<int16_t>(gl), -1, 0, 0};
                 st.recs.assign(Q, GroupRec{-1, 0, 0, 0});
                 int64_t max_n = 0;
                 for (int k = 0; k < per && pos < light.size() && (light[pos].first >> 32) == gl; ++k, ++pos) {

@@ -146,6 +146,9 @@ psgld_status load_job(psgld_server *srv, Job *j)
     o.device = srv->opt.device;
     o.graph_iters = -1;
     o.persistent = srv->opt.persistent ? 1 : 0;
+    o.dev_alloc = srv->opt.dev_alloc;
+    o.dev_free = srv->opt.dev_free;
+    o.alloc_user = srv->opt.alloc_user;
     psgld_status st = psgld_create(s.I, s.J, s.K, s.B, &s.lik, &s.prior, &o, &j->ctx);
     if (st) {
         j->err = psgld_last_error(nullptr);
@@ -208,7 +211,8 @@ psgld_status psgld_server_create(const psgld_server_options *opt, psgld_server *
 {
     if (!opt || !out) return PSGLD_E_ARG;
     *out = nullptr;
-    if (opt->hbm_budget <= 0 || opt->max_active < 1 || opt->iters_per_tick < 1 || opt->device < 0)
+    if (opt->hbm_budget <= 0 || opt->max_active < 1 || opt->iters_per_tick < 1 || opt->device < 0 ||
+        (opt->dev_alloc == nullptr) != (opt->dev_free == nullptr))
         return PSGLD_E_ARG;
     psgld_server *srv = new (std::nothrow) psgld_server();
     if (!srv) return PSGLD_E_NOMEM;

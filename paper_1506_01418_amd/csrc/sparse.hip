@@ -365,11 +365,27 @@ __device__ __forceinline__ void sparse_task(const SparseIterArgs &a, const IterS
     }
     // Items split over work-groups: publish this share; the last share to
     // arrive sums all shares in slot order.  Only the partials cross
-    // work-groups, so instead of a release/acquire pair (which writes back
-    // and invalidates the whole L2 of the XCD) they are written through to
-    // memory with system-scope stores, complete (vmcnt 0) before the
-    // share's arrival is counted, and read back with system-scope loads
-    // by the last share, after its count shows every other arrival.
+    // work-groups, so instead of a release/acquire pair (an agent-scope
+    // release writes back, and an acquire invalidates, the whole L2 of the
+    // XCD, which would evict the partner rows other work-groups are
+    // gathering) the ordering is made at the level of the gfx950 ISA:
+    //  1. the partials are relaxed system-scope atomic stores, which compile
+    //     to global_store_dword ... sc0 sc1: written through every cache
+    //     level to memory;
+    //  2. s_waitcnt vmcnt(0) holds the wave until each of those stores has
+    //     been acknowledged at that scope, and the work-group barrier holds
+    //     thread 0 until every wave has done so;
+    //  3. only then does thread 0 count the arrival with an agent-scope
+    //     atomic add (atomic across all XCDs of the device);
+    //  4. the share that sees the count n_split - 1 reads every partial with
+    //     relaxed system-scope loads (global_load_dword ... sc0 sc1: no cache
+    //     level answers them), issued after the add has returned, since
+    //     which share reads depends on the value it returned.
+    // So every partial a last share reads was in memory before its writer's
+    // arrival was counted.  This rests on the ISA's cache-bypass bits, not
+    // on a happens-before edge of the HIP memory model.  Tested by stepping
+    // Zipf(1.1)-skewed chains with items cut into dozens of shares and
+    // comparing every single step with the FP64 oracle.
     bool lead = rec.item >= 0 && rec.lead;
     if (task.n_split > 0) {
         float *slot = a.split_partial + static_cast<size_t>(task.split_first + task.split_idx) * a.Kp;
@@ -526,6 +542,9 @@ __global__ __launch_bounds__(kBlockThreads) void sparse_persistent_kernel(BatchA
             const int j = job_of(b.wg_first, b.n, v);
             const JobDesc &d = *b.jobs[j];
             job_task<LPG, QPL, LIK>(d, *d.clock + k, v - b.wg_first[j]);
+            // the next task reuses the LDS partials of this one: every
+            // wave must have read them before any wave writes again
+            __syncthreads();
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's stores have reached L2
         __syncthreads();
@@ -571,15 +590,18 @@ hipError_t launch_persistent_lpg(const BatchArgs &b, int n_iter, int lik, int gr
     case LIK_GAMMA: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_GAMMA>); break;
     default: f = reinterpret_cast<const void *>(&sparse_persistent_kernel<LPG, QPL, LIK_GENERAL>); break;
     }
-    if (grid <= 0) {
-        // as many work-groups as the device holds at once, and no more than there is work
+    {
+        // at most as many work-groups as the device holds at once (every one
+        // must be resident for the grid barrier), and no more than there is
+        // work; a smaller grid when asked
         int dev = 0, per_cu = 0;
         hipDeviceProp_t prop;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
         if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlockThreads, 0);
         if (e != hipSuccess) return e;
-        grid = std::min(per_cu * prop.multiProcessorCount, b.wg_first[b.n]);
+        const int resident = std::min(per_cu * prop.multiProcessorCount, b.wg_first[b.n]);
+        grid = grid > 0 ? std::min(grid, resident) : resident;
     }
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(reset_barrier_kernel, dim3(1), dim3(64), 0, stream, barrier);

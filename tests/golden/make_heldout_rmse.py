@@ -55,9 +55,10 @@ def main(names):
     for name in names:
         data[name] = oracle_rmse(name)
         print(f"[golden] {name}: RMSE {data[name]['heldout_rmse']:.6f}", file=sys.stderr, flush=True)
-        with open(OUT, "w") as f:
+        with open(OUT + ".tmp", "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
             f.write("\n")
+        os.replace(OUT + ".tmp", OUT)
 
 
 if __name__ == "__main__":

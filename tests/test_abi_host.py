@@ -127,3 +127,51 @@ def test_balanced_pieces_even_out_zipf_parts():
 def workloads_small_zipf():
     import workloads
     return workloads.random_sparse(3000, 800, 80_000, 8, 8, zipf_a=1.2, data_seed=17, chain_seed=18)
+
+
+def test_default_options_have_no_allocator_hooks():
+    o = pkg.psgld_default_options()
+    assert o.persistent_grid == 0 and not o.dev_alloc and not o.dev_free and o.alloc_user is None
+
+
+def test_create_rejects_one_allocator_hook_alone():
+    alloc = pkg.DEV_ALLOC_FN(lambda n, u: None)
+    free = pkg.DEV_FREE_FN(lambda p, n, u: None)
+    lik = pkg.psgld_likelihood(2.0, 1.0)
+    pr = pkg.psgld_prior(pkg.PSGLD_PRIOR_GAUSSIAN, 1.0, 1.0, 0)
+    for a, f in [(alloc, None), (None, free)]:
+        o = pkg.psgld_default_options()
+        if a:
+            o.dev_alloc = a
+        if f:
+            o.dev_free = f
+        with pytest.raises(pkg.PsgldError, match="go together"):
+            pkg.psgld_create(5, 5, 2, 1, lik, pr, o)
+    o = pkg.psgld_default_options()
+    o.persistent_grid = -1
+    with pytest.raises(pkg.PsgldError, match="persistent_grid"):
+        pkg.psgld_create(5, 5, 2, 1, lik, pr, o)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of psgld_options, psgld_server_options and psgld_job
+    have the C header's field offsets and sizes (compiled with gcc here)."""
+    structs = {"psgld_options": pkg.psgld_options, "psgld_server_options": pkg.psgld_server_options,
+               "psgld_job": pkg.psgld_job}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psgld.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

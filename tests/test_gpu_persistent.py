@@ -101,3 +101,21 @@ def test_persistent_serving_matches_alone():
             assert np.array_equal(x, y)
         s.close()
     srv.close()
+
+
+@pytest.mark.parametrize("grid", [1, 7])
+def test_persistent_small_grid_matches_single_launches(grid):
+    """Persistent launches with far fewer work-groups than tasks: each
+    work-group runs many tasks of an iteration in turn, and the tasks of
+    Zipf-skewed columns combine their groups' partial sums in LDS, which the
+    next task of the same work-group reuses.  Bitwise equal to per-iteration
+    launches."""
+    wl = CASES["K50_zipf"]()
+    eager = pkg.PSGLD.from_workload(wl, burn_in=5, thin=2, graph_iters=-1)
+    pers = pkg.PSGLD.from_workload(wl, burn_in=5, thin=2, persistent=1, persistent_grid=grid)
+    for n in (2, 19):
+        eager.step(n, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        pers.step(n, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+    _assert_same(eager, pers)
+    eager.close()
+    pers.close()

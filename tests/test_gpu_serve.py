@@ -91,3 +91,30 @@ def test_admission_respects_budget_and_order():
     assert e.value.status == pkg.PSGLD_E_ARG
     small.close()
     srv.close()
+
+
+def test_served_jobs_track_the_oracle():
+    """Jobs served in a mix against the FP64 oracle run of each job: over 40
+    iterations (burn-in 12, thinning 2) FP32 and FP64 chains stay close, so
+    each job's posterior mean and variance and its held-out RMSE agree
+    with the oracle's (rtol 1e-4, as for a context stepped alone)."""
+    import oracle
+    from parity import oracle_config
+    wls = _mix()
+    srv = pkg.Server(hbm_budget=8 << 30, max_active=4, iters_per_tick=7)
+    ids = [srv.submit(wl, N_ITER, dense=_is_dense(wl), dense_min_cols=1) for wl in wls]
+    _drain(srv)
+    for jid, wl in zip(ids, wls):
+        Wm, Hm, Wv, Hv, rmse = srv.result(jid)
+        ch = oracle.Chain(oracle_config(wl), wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+        ch.run(N_ITER)
+        rW, rH = ch.posterior_mean()
+        qW, qH = ch.posterior_var()
+        # the BF16-free dense job runs FP32 MFMA products: same tolerance
+        np.testing.assert_allclose(Wm, rW, rtol=1e-4, atol=1e-6)
+        np.testing.assert_allclose(Hm, rH, rtol=1e-4, atol=1e-6)
+        assert np.all(np.abs(Wv - qW) <= 1e-4 * (rW ** 2 + qW) + 1e-9)
+        assert np.all(np.abs(Hv - qH) <= 1e-4 * (rH ** 2 + qH) + 1e-9)
+        assert rmse == pytest.approx(ch.heldout_rmse(wl.hval), rel=1e-4)
+        srv.release(jid)
+    srv.close()
