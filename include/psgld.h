@@ -223,6 +223,25 @@ psgld_status psgld_step(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule
 psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *n_iter,
                               const psgld_eps_schedule *scheds);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. a tight serving loop or a harness that forbids it): the
+ * same iterations as psgld_step, from the same kernels and bitwise the same
+ * results, with no device or host allocation in the call.  The scratch those
+ * kernels use beside the context's own arrays -- the partial gradients and
+ * arrival counters of items cut over several work-groups, and this call's
+ * step sizes -- lives in one static 16 MiB device array per GPU, held until
+ * the process ends.  Per call at most 65536 iterations (E_ARG beyond); only
+ * contexts without dense blocks (E_UNSUPPORTED), whose schedule's split
+ * shares fit the array: at most 65536 shares of Kp floats within 15.25 MiB
+ * (E_UNSUPPORTED beyond).  Waits for the context's queued work before it
+ * overwrites the step sizes, then runs asynchronously on the context's
+ * stream like psgld_step (per-iteration launches; no graph, no persistent
+ * launch).  Calls on one GPU share the array: two calls whose work overlaps
+ * on the device (different streams or threads) race and give wrong results,
+ * so callers serialise them.  The context itself is created and loaded as
+ * usual beforehand. */
+psgld_status psgld_step_static(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule *sched);
+
 /* Tunes the work schedule of the coordinate-stored blocks (how many entries
  * one lane group takes before an item is spread over more groups) on this
  * context's own data.  With n > 1, each candidate in candidates[0..n) is

@@ -150,6 +150,7 @@ SIGNATURES = {
     "psgld_load_heldout": ([_P, _I64, _P, _P, _P], _ST),
     "psgld_set_factors": ([_P, _P, _P], _ST),
     "psgld_step": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
+    "psgld_step_static": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
     "psgld_step_batch": ([_P, C.c_int32, _P, _P], _ST),
     "psgld_sync": ([_P], _ST),
     "psgld_tune": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(psgld_eps_schedule), C.POINTER(C.c_int32)], _ST),
@@ -257,6 +258,10 @@ def psgld_set_factors(ctx, W, H):
 
 def psgld_step(ctx, n_iter, sched: psgld_eps_schedule):
     _check(lib().psgld_step(ctx, int(n_iter), C.byref(sched)), ctx)
+
+
+def psgld_step_static(ctx, n_iter, sched: psgld_eps_schedule):
+    _check(lib().psgld_step_static(ctx, int(n_iter), C.byref(sched)), ctx)
 
 
 def psgld_step_batch(ctxs, n_iter, scheds):

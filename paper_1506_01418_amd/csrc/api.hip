@@ -75,6 +75,7 @@ struct psgld_ctx {
     int64_t N = 0;
     std::vector<int64_t> n_p;
     std::vector<int64_t> task_off, n_tasks;
+    int32_t max_splits = 0;           // split-share slots the largest part needs
 
     std::map<void *, size_t> allocs;   // device blocks of the context and their sizes
     int64_t bytes = 0;
@@ -340,6 +341,7 @@ psgld_status upload_schedule(psgld_ctx *c)
     if ((s = upload(c, &c->task_off_dev, toff))) return s;
     if ((s = upload(c, &c->n_tasks_dev, ntk))) return s;
     c->job_valid = false;
+    c->max_splits = max_splits;
     if ((s = dev_alloc(c, &c->split_partial, static_cast<size_t>(max_splits) * c->Kp))) return s;
     if ((s = dev_alloc(c, &c->split_count, static_cast<size_t>(max_splits)))) return s;
     HIPTRY(c, hipMemset(c->split_count, 0, std::max<int32_t>(max_splits, 1) * sizeof(int32_t)));
@@ -601,12 +603,21 @@ psgld_status ensure_eps_table(psgld_ctx *c, const psgld_eps_schedule *sched, int
 // iteration index is *clock + k when clock is given (captured graphs), else
 // k.  With bookkeeping off (tuning trials) no moments or held-out sums are
 // touched.
+// Device buffers an iteration reads beside the context's own arrays: the
+// step-size table (indexed by the global iteration) and the scratch of items
+// cut over several work-groups.  Null: the context's.
+struct IterBuffers {
+    const float2 *eps_tab;
+    float *split_partial;
+    int32_t *split_count;
+};
+
 hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *clock, int32_t k, bool bookkeeping,
-                             hipStream_t stream)
+                             hipStream_t stream, const IterBuffers *buf = nullptr)
 {
     const int64_t I = c->I, J = c->J;
     IterClock clk{};
-    clk.eps_tab = c->eps_tab - c->eps_base;   // indexed by the global iteration
+    clk.eps_tab = buf ? buf->eps_tab : c->eps_tab - c->eps_base;   // indexed by the global iteration
     clk.clock = clock;
     clk.k = k;
     clk.burn_in = static_cast<int32_t>(std::min<int64_t>(c->opt.burn_in, INT32_MAX));
@@ -624,8 +635,8 @@ hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *cl
     a.tasks = c->tasks + c->task_off[p];
     a.recs = c->recs + static_cast<size_t>(c->task_off[p]) * (sparse_block_threads() / c->lpg);
     a.n_tasks = static_cast<int32_t>(c->n_tasks[p]);
-    a.split_partial = c->split_partial;
-    a.split_count = c->split_count;
+    a.split_partial = buf ? buf->split_partial : c->split_partial;
+    a.split_count = buf ? buf->split_count : c->split_count;
     a.K = c->K;
     a.Kp = c->Kp;
     a.nq = c->nq;
@@ -1322,6 +1333,95 @@ psgld_status psgld_step(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *
     return PSGLD_OK;
 }
 
+}  // extern "C"
+
+// ---- allocation-free stepping (psgld_step_static) -------------------------
+namespace {
+constexpr size_t kScratchBytes = size_t{16} << 20;
+}  // namespace
+
+// Scratch of psgld_step_static, one copy per device for the life of the
+// process: the arrival counters of items cut over several work-groups, the
+// step-size window of one call, and the partial gradients of the shares.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr size_t kScratchCounters = size_t{1} << 16;                  // int32 at byte 0
+constexpr size_t kScratchEpsOffset = kScratchCounters * sizeof(int32_t);
+constexpr size_t kScratchEps = size_t{1} << 16;                       // float2: iterations per call
+constexpr size_t kScratchPartialOffset = kScratchEpsOffset + kScratchEps * sizeof(float2);
+constexpr size_t kScratchPartialFloats = (kScratchBytes - kScratchPartialOffset) / sizeof(float);
+static_assert(kScratchPartialOffset % 256 == 0, "scratch regions stay 256-byte aligned");
+
+std::mutex g_scratch_mutex;
+std::map<int, unsigned char *> g_scratch_addr;   // device -> device address of its `scratch`
+float2 g_static_eps[kScratchEps];                // host staging of one call's step sizes (under the mutex)
+
+// The device address of `scratch` on the current device `dev`.  The name
+// itself is a host-side stand-in; only this address may be used from host
+// code.  Looked up once per device.
+psgld_status scratch_address(psgld_ctx *c, int dev, unsigned char **out)
+{
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return c->fail(PSGLD_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_addr.emplace(dev, static_cast<unsigned char *>(ptr)).first;
+    }
+    *out = it->second;
+    return PSGLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psgld_status psgld_step_static(psgld_ctx *c, int64_t n_iter, const psgld_eps_schedule *sched)
+{
+    if (!c) return PSGLD_E_ARG;
+    psgld_status s = check_schedule(c, sched);
+    if (s) return s;
+    if (n_iter < 0 || n_iter > static_cast<int64_t>(kScratchEps))
+        return c->fail(PSGLD_E_ARG, "n_iter must be in [0, 65536]");
+    if (!c->loaded || !c->factors_set) return c->fail(PSGLD_E_STATE, "load data and set factors first");
+    if (c->t + n_iter >= INT32_MAX) return c->fail(PSGLD_E_ARG, "iteration counter would exceed 2^31");
+    if (!c->dblocks_host.empty())
+        return c->fail(PSGLD_E_UNSUPPORTED, "psgld_step_static runs coordinate-stored blocks only");
+    if (static_cast<size_t>(c->max_splits) > kScratchCounters ||
+        static_cast<size_t>(c->max_splits) * c->Kp > kScratchPartialFloats)
+        return c->fail(PSGLD_E_UNSUPPORTED, "the schedule's split shares need more than the 16 MiB of static scratch");
+    if (n_iter == 0) return PSGLD_OK;
+    HIPTRY(c, use_device(c->opt.device));
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    unsigned char *base = nullptr;
+    if ((s = scratch_address(c, c->opt.device, &base))) return s;
+    int32_t *counters = reinterpret_cast<int32_t *>(base);
+    float2 *eps_dev = reinterpret_cast<float2 *>(base + kScratchEpsOffset);
+    float *partials = reinterpret_cast<float *>(base + kScratchPartialOffset);
+    // the step sizes of t .. t + n_iter - 1, computed as psgld_step computes
+    // them; this context's earlier work may still read the window
+    const int64_t t0 = c->t;
+    for (int64_t k = 0; k < n_iter; ++k) {
+        const double eps = sched->a * std::pow(sched->t0 + static_cast<double>(t0 + k), -sched->gamma);
+        g_static_eps[k] = make_float2(static_cast<float>(eps), static_cast<float>(std::sqrt(2.0 * eps)));
+    }
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    HIPTRY(c, hipMemcpy(eps_dev, g_static_eps, static_cast<size_t>(n_iter) * sizeof(float2), hipMemcpyHostToDevice));
+    // arrival counters start at zero (the kernels leave them at zero, but the
+    // array is shared with every other call on this device)
+    HIPTRY(c, launch_fill_i32(counters, 0, std::max<int32_t>(c->max_splits, 1), c->stream));
+    const IterBuffers buf{eps_dev - t0, partials, counters};
+    for (int64_t k = 0; k < n_iter; ++k) {
+        HIPTRY(c, enqueue_iteration(c, part_at(c, c->t), c->cur, nullptr, static_cast<int32_t>(c->t), true,
+                                    c->stream, &buf));
+        account_iteration(c, c->t);
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    return PSGLD_OK;
+}
 
 namespace {
 

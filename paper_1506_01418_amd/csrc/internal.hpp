@@ -310,5 +310,7 @@ hipError_t launch_sum_in_order(const double *partials, int n, double *out, hipSt
 // *clock = value, and *clock += delta, as kernels (so both can be captured).
 hipError_t launch_set_clock(int32_t *clock, int32_t value, hipStream_t stream);
 hipError_t launch_advance_clock(int32_t *clock, int32_t delta, hipStream_t stream);
+// p[0 .. n) = value, as a kernel (no memset node when captured).
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t stream);
 
 }  // namespace psgld

@@ -1,5 +1,6 @@
 // Small kernels beside the sampler: evaluation of the noise stream for
 // given counters, and the FP64 training log-likelihood reduction.
+#include <algorithm>
 #include "internal.hpp"
 #include "noise.hpp"
 
@@ -60,6 +61,13 @@ __global__ void set_clock_kernel(int32_t *clock, int32_t value)
 __global__ void advance_clock_kernel(int32_t *clock, int32_t delta)
 {
     if (threadIdx.x == 0) *clock += delta;
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t n)
+{
+    for (int64_t m = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; m < n;
+         m += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[m] = value;
 }
 
 constexpr int kLLThreads = 256;
@@ -196,6 +204,14 @@ hipError_t launch_set_clock(int32_t *clock, int32_t value, hipStream_t stream)
 hipError_t launch_advance_clock(int32_t *clock, int32_t delta, hipStream_t stream)
 {
     hipLaunchKernelGGL(advance_clock_kernel, dim3(1), dim3(64), 0, stream, clock, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, p, value, n);
     return hipGetLastError();
 }
 
