@@ -183,6 +183,19 @@ def stored_oracle_rmse(wl):
     return ref["heldout_rmse"]
 
 
+def stored_oracle_trace(wl, every):
+    """Mean training log-likelihood of the oracle's whole run over the trace
+    points of its second half, from tests/golden/ll_trace.json, or None."""
+    path = os.path.join(ROOT, "tests", "golden", "ll_trace.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f).get(wl.name)
+    if not ref or ref["T"] != wl.T or ref["every"] != every:
+        return None
+    return float(np.mean([p[1] for p in ref["points"] if p[0] > wl.T // 2]))
+
+
 def make_workload(name):
     try:
         return workloads.by_name(name)
@@ -314,6 +327,9 @@ def main():
                     help="oracle iterations on one thread for the CPU baseline")
     ap.add_argument("--no-full-chain", action="store_true",
                     help="skip the whole-chain pass (held-out RMSE after T iterations)")
+    ap.add_argument("--trace-every", type=int, default=0,
+                    help="mixing trace: a whole-chain pass recording the training log-likelihood every this "
+                         "many iterations against the sampler's time (0: off)")
     ap.add_argument("--cpu-iters", type=int, default=0, help="exact oracle iterations instead (0: by time)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
@@ -483,6 +499,30 @@ def main():
         print(f"[bench] pass 3: whole chain of {wl.T} iterations in {chain_ms:.2f} ms "
               f"({chain['updates_per_s']:.4g} updates/s), held-out RMSE {chain_rmse:.6f}"
               f" (oracle {ref})", file=sys.stderr, flush=True)
+    # pass 4: the mixing indicator of the paper's synthetic experiments, the
+    # log-likelihood of the chain's state against time (Section 4.2.1)
+    trace = None
+    if args.trace_every > 0:
+        s.set_state(state0)
+        ev.sync()
+        points, sampler_ms, t = [[0, 0.0, s.log_likelihood()]], 0.0, 0
+        while t < wl.T:
+            n = min(args.trace_every, wl.T - t)
+            ea, eb = ev.create(2)
+            ev.record(ea, stream)
+            s.step(n, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+            ev.record(eb, stream)
+            sampler_ms += ev.elapsed_ms(ea, eb)
+            t += n
+            points.append([t, sampler_ms, s.log_likelihood()])
+        ref = stored_oracle_trace(wl, args.trace_every)
+        half = [p[2] for p in points if p[0] > wl.T // 2]
+        trace = {"every": args.trace_every, "T": wl.T, "sampler_ms": sampler_ms, "points": points,
+                 "loglik_mean_second_half": float(np.mean(half)) if half else None,
+                 "oracle_loglik_mean_second_half": ref}
+        print(f"[bench] pass 4: trace of {len(points)} log-likelihoods over {wl.T} iterations "
+              f"({sampler_ms:.1f} ms of sampling), second-half mean {trace['loglik_mean_second_half']:.6g} "
+              f"(oracle {ref})", file=sys.stderr, flush=True)
     s.close()
 
     cpu = None
@@ -513,6 +553,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if trace:
+        out["mixing_trace"] = trace
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
         import torch

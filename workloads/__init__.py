@@ -249,14 +249,7 @@ def dense_tweedie(I=1025, J=100_000, K_true=64, K=64, B=16, heldout=0.1, data_se
     rng = np.random.default_rng(data_seed)
     Wt = rng.gamma(2.0, 1.0, (I, K_true)).astype(np.float32)
     Ht = rng.gamma(0.5, 1.0, (K_true, J)).astype(np.float32)
-    V = np.empty((I, J), dtype=np.float32)
-    rows_per = max(1, (1 << 22) // J)
-    for r0 in range(0, I, rows_per):
-        mu = (Wt[r0:r0 + rows_per].astype(np.float64) @ Ht.astype(np.float64))
-        sq = np.sqrt(mu)
-        n = rng.poisson(2.0 * sq)
-        g = rng.gamma(np.maximum(n, 1), 0.5 * sq)
-        V[r0:r0 + rows_per] = np.where(n > 0, g, 0.0)
+    V = compound_poisson_matrix(rng, Wt, Ht)
     cells = I * J
     tr, ho = _split_heldout(rng, cells, heldout)
     mask = np.zeros(cells, dtype=np.uint8)
@@ -271,6 +264,45 @@ def dense_tweedie(I=1025, J=100_000, K_true=64, K=64, B=16, heldout=0.1, data_se
     return Workload(name, I, J, K, B, 0.5, 1.0, "exponential", 1.0, 1.0, True,
                     a, 1.0, 0.51, chain_seed, T, burn_in, thin,
                     row, col, val, hrow, hcol, hval, W0, H0, dense=V, mask=mask)
+
+
+def compound_poisson_matrix(rng, Wt, Ht):
+    """V ~ TW(mu = Wt Ht, phi = 1, beta = 0.5): the Tweedie law of power
+    p = 2 - beta = 1.5 is a compound Poisson-gamma, v = sum of N ~ Pois(2
+    sqrt(mu)) gamma variables of shape 1 and scale sqrt(mu) / 2 (v = 0 when
+    N = 0), drawn a few million cells at a time."""
+    I, J = Wt.shape[0], Ht.shape[1]
+    V = np.empty((I, J), dtype=np.float32)
+    rows_per = max(1, (1 << 22) // J)
+    for r0 in range(0, I, rows_per):
+        mu = (Wt[r0:r0 + rows_per].astype(np.float64) @ Ht.astype(np.float64))
+        sq = np.sqrt(mu)
+        n = rng.poisson(2.0 * sq)
+        g = rng.gamma(np.maximum(n, 1), 0.5 * sq)
+        V[r0:r0 + rows_per] = np.where(n > 0, g, 0.0)
+    return V
+
+
+def paper_compound_poisson(I=1024, J=1024, K=32, B=32, data_seed=1013, chain_seed=2013, T=10_000,
+                           burn_in=5_000, thin=10, name="paper_cpoisson_1024"):
+    """The paper's compound Poisson experiment (Section 4.2.1): W, H drawn
+    from the model's exponential priors (rate 1), V ~ TW(WH, phi = 1,
+    beta = 0.5), every cell observed; fit with the same model (exponential
+    priors, mirroring), K = 32, B = I / 32."""
+    rng = np.random.default_rng(data_seed)
+    Wt = rng.gamma(1.0, 1.0, (I, K)).astype(np.float32)
+    Ht = rng.gamma(1.0, 1.0, (K, J)).astype(np.float32)
+    V = compound_poisson_matrix(rng, Wt, Ht)
+    row, col = np.nonzero(np.ones((I, J), dtype=bool))
+    row, col = row.astype(np.int32), col.astype(np.int32)
+    val = V.reshape(-1)
+    empty = np.zeros(0, dtype=np.int32)
+    a = step_scale(row, col, val, I, J, 0.5, 1.0)
+    W0, H0 = init_factors(np.random.default_rng(chain_seed), I, J, K, float(val.mean()), True)
+    return Workload(name, I, J, K, B, 0.5, 1.0, "exponential", 1.0, 1.0, True,
+                    a, 1.0, 0.51, chain_seed, T, burn_in, thin,
+                    row, col, val, empty, empty, np.zeros(0, dtype=np.float32), W0, H0,
+                    dense=V, mask=np.ones((I, J), dtype=np.uint8))
 
 
 def random_sparse(I, J, nnz, K, B, beta=2.0, phi=1.0, prior="gaussian", mirror=False,
@@ -398,6 +430,13 @@ def by_name(name):
                            T=10_000, burn_in=5_000, thin=10, name=name)
         wl.eps_a = step_scale(wl.row, wl.col, wl.val, wl.I, wl.J, wl.beta, wl.phi)
         return wl
+    elif name == "paper_poisson_512":
+        wl = dense_poisson(I=512, J=512, K=32, B=16, heldout=0.0, data_seed=1012, chain_seed=2012,
+                           T=10_000, burn_in=5_000, thin=10, name=name)
+        wl.eps_a = step_scale(wl.row, wl.col, wl.val, wl.I, wl.J, wl.beta, wl.phi)
+        return wl
+    elif name == "paper_cpoisson_1024":
+        return paper_compound_poisson()
     elif name == "paper_spectrum_256":
         return dense_poisson(I=256, J=256, K=8, B=8, heldout=0.0, data_seed=1011, chain_seed=2011,
                              T=10_000, burn_in=5_000, thin=10, eps_a=1e-3, eps_t0=1.0, eps_gamma=0.51, name=name)
