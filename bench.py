@@ -121,13 +121,13 @@ def part_work(wl, dense, cnt, rows, cols):
 def algorithmic_cost(wl, cells_p, entries_p, ho_p, t, p):
     """(bytes, flops) one iteration must move and compute at minimum: each
     training entry of the part's coordinate blocks read once (4-byte index +
-    4-byte value), each cell of its dense blocks read once (FP32 value + mask
-    byte), every factor element read and written once in FP32, the FP64 sums
-    of x and x^2 read and written at kept iterations, one FP64
-    read-modify-write per held-out cell of the part after burn-in; 6K flops
-    per dense cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the part
-    of iteration t."""
-    b = 5 * cells_p[p] + 8 * entries_p[p] + 8 * (wl.I + wl.J) * wl.K
+    4-byte value), each cell of its dense blocks read once (FP32 value + one
+    bit of training mask), every factor element read and written once in
+    FP32, the FP64 sums of x and x^2 read and written at kept iterations, one
+    FP64 read-modify-write per held-out cell of the part after burn-in; 6K
+    flops per dense cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the
+    part of iteration t."""
+    b = 4.125 * cells_p[p] + 8 * entries_p[p] + 8 * (wl.I + wl.J) * wl.K
     if t >= wl.burn_in:
         b += 16 * ho_p[p]
         if (t - wl.burn_in) % wl.thin == 0:
@@ -393,13 +393,14 @@ def main():
         placed = np.zeros((wl.B, wl.B), dtype=bool)
         cells_p, entries_p = np.zeros(wl.B, dtype=np.int64), np.asarray(n_p, dtype=np.int64)
     runs_dense, runs_sparse = bool(placed.any()), not bool(placed.all())
-    chosen = None
+    chosen, sched_info = None, (None, None, None)
     if runs_sparse:
         t_tune = time.perf_counter()
         cands = (args.entries_per_group,) if args.entries_per_group > 0 else (16, 32, 64, 128)
         chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=cands, iters=wl.B)
-        print(f"[bench] tuned entries per group: {chosen} ({time.perf_counter() - t_tune:.1f} s)",
-              file=sys.stderr, flush=True)
+        sched_info = s.schedule_info()
+        print(f"[bench] tuned schedule: {chosen} entries per group, {sched_info[1]} quads per lane, "
+              f"{sched_info[2]} lanes per group ({time.perf_counter() - t_tune:.1f} s)", file=sys.stderr, flush=True)
     rpc = pieces.get("row_piece", pkg_pieces(wl, "row"))
     cpc = pieces.get("col_piece", pkg_pieces(wl, "col"))
     ho_part = (np.asarray(cpc)[wl.hcol] - np.asarray(rpc)[wl.hrow]) % wl.B
@@ -473,6 +474,9 @@ def main():
                  "alg_bytes_per_launch": float(alg.mean())})
     if runs_dense:
         roof["flops_per_launch"] = float(flops.mean())
+        # beside the HBM fraction: how busy the products keep the matrix cores
+        roof["mfma_frac"] = float(flops.mean()) / (avg_ms * 1e-3) / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
+        roof["hbm_frac"] = float(alg.mean()) / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
     print(f"[bench] pass 2: iteration avg {float(durs.mean()) * 1e3:.2f} us with events around each launch; "
           f"timed region {avg_ms * 1e3:.2f} us per iteration, roofline {roof['achieved']:.1f} "
           f"{roof['unit']} ({roof['bound']}), RMSE {rmse2}", file=sys.stderr, flush=True)
@@ -544,7 +548,8 @@ def main():
                    "timed_iterations": args.steps, "T": wl.T, "burn_in": wl.burn_in, "thin": wl.thin,
                    "heldout_rmse": chain["heldout_rmse"] if chain else rmse,
                    "oracle_heldout_rmse": chain["oracle_heldout_rmse"] if chain else None,
-                   "whole_chain": chain, "train_loglik_end": loglik, "entries_per_group": chosen, "dense": runs_dense,
+                   "whole_chain": chain, "train_loglik_end": loglik, "entries_per_group": chosen,
+                   "quads_per_lane": sched_info[1], "lanes_per_group": sched_info[2], "dense": runs_dense,
                    "dense_blocks": int(placed.sum()),
                    "precision": args.precision if runs_dense else "f32", "parallelism": "single-gpu",
                    "part_order": args.part_order, "balanced_pieces": bool(pieces),

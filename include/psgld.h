@@ -242,19 +242,33 @@ psgld_status psgld_step_batch(psgld_ctx *const *ctxs, int32_t n, const int64_t *
  * usual beforehand. */
 psgld_status psgld_step_static(psgld_ctx *ctx, int64_t n_iter, const psgld_eps_schedule *sched);
 
-/* Tunes the work schedule of the coordinate-stored blocks (how many entries
- * one lane group takes before an item is spread over more groups) on this
- * context's own data.  With n > 1, each candidate in candidates[0..n) is
- * timed over `iters` iterations (iters < 1: one cycle of B parts) from the
- * current state with schedule `sched`; the state is restored afterwards, so
- * the chain is unchanged, and the fastest candidate is kept and remembered
- * for this shape (in-process, and in the file named by the environment
- * variable PSGLD_TUNE_CACHE if set, which later contexts of the same shape
- * read at load).  With n == 1 the candidate is simply applied.  Results are
- * bitwise reproducible for a fixed choice; different choices change the FP32
- * summation order.  *chosen (may be NULL) receives the value kept.  Syncs. */
+/* Tunes the work schedule of the coordinate-stored blocks on this context's
+ * own data: how many entries one lane group takes before an item is spread
+ * over more groups (the candidates), and the kernel variant -- how many
+ * 4-element pieces of a row each lane holds (1, 2 or 4), which sets how many
+ * lanes share an item.  With n > 1, each candidate in candidates[0..n) is
+ * timed with every variant built for this rank, over `iters` iterations
+ * (iters < 1: one cycle of B parts) from the current state with schedule
+ * `sched`; the state is restored afterwards, so the chain is unchanged, and
+ * the fastest pair is kept and remembered for this shape (in-process, and in
+ * the file named by the environment variable PSGLD_TUNE_CACHE if set, which
+ * later contexts of the same shape read at load).  With n == 1 the candidate
+ * is applied with the current variant.  Results are bitwise reproducible for
+ * a fixed choice; different choices change the FP32 summation order.
+ * *chosen (may be NULL) receives the entries per group kept.  Syncs. */
 psgld_status psgld_tune(psgld_ctx *ctx, const int32_t *candidates, int32_t n, int32_t iters,
                         const psgld_eps_schedule *sched, int32_t *chosen);
+
+/* Sets the sparse schedule directly (what psgld_tune chooses): entries per
+ * lane group >= 1 and quads per lane 1, 2 or 4 (0: the default for the rank);
+ * E_ARG if no kernel variant covers the rank with that many quads per lane.
+ * Needs loaded data (E_STATE).  Waits for queued work. */
+psgld_status psgld_set_schedule(psgld_ctx *ctx, int32_t entries_per_group, int32_t quads_per_lane);
+
+/* The sparse schedule in use: entries per lane group, quads per lane and
+ * lanes per item group (any output may be NULL). */
+psgld_status psgld_schedule_info(psgld_ctx *ctx, int32_t *entries_per_group, int32_t *quads_per_lane,
+                                 int32_t *lanes_per_group);
 
 /* Blocks until the context's queued work is done.  E_NUMERIC (with the
  * first iteration index in the message) if a non-finite value appeared. */

@@ -153,6 +153,8 @@ SIGNATURES = {
     "psgld_step_static": ([_P, _I64, C.POINTER(psgld_eps_schedule)], _ST),
     "psgld_step_batch": ([_P, C.c_int32, _P, _P], _ST),
     "psgld_sync": ([_P], _ST),
+    "psgld_set_schedule": ([_P, C.c_int32, C.c_int32], _ST),
+    "psgld_schedule_info": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], _ST),
     "psgld_tune": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(psgld_eps_schedule), C.POINTER(C.c_int32)], _ST),
     "psgld_get_factors": ([_P, _P, _P], _ST),
     "psgld_posterior_mean": ([_P, _P, _P], _ST),
@@ -299,6 +301,13 @@ def psgld_tune(ctx, candidates, iters, sched: psgld_eps_schedule) -> int:
     out = C.c_int32()
     _check(lib().psgld_tune(ctx, _ptr(cand), len(cand), int(iters), C.byref(sched), C.byref(out)), ctx)
     return out.value
+
+
+def psgld_schedule_info(ctx):
+    """(entries per group, quads per lane, lanes per group) of the sparse schedule."""
+    e, q, l_ = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().psgld_schedule_info(ctx, C.byref(e), C.byref(q), C.byref(l_)), ctx)
+    return e.value, q.value, l_.value
 
 
 def psgld_sync(ctx):
@@ -506,6 +515,12 @@ class PSGLD:
 
     def sync(self):
         psgld_sync(self.ctx)
+
+    def schedule_info(self):
+        return psgld_schedule_info(self.ctx)
+
+    def set_schedule(self, entries_per_group, quads_per_lane=0):
+        _check(lib().psgld_set_schedule(self.ctx, int(entries_per_group), int(quads_per_lane)), self.ctx)
 
     def factors(self):
         return psgld_get_factors(self.ctx, self.I, self.J, self.K)

@@ -113,7 +113,8 @@ struct psgld_ctx {
     DenseBlock *dblocks = nullptr;
     DenseTile *dtiles = nullptr;
     float *dval = nullptr;
-    uint8_t *dmask = nullptr;
+    uint32_t *dmask = nullptr;              // 2-bit cell codes of the dense blocks
+    std::vector<uint32_t> dcodes_host;      // their host copy
     float *w_partial = nullptr;
     DenseHeld *dheld = nullptr;
     int dense_max_m = 0, KS = 0;
@@ -361,45 +362,57 @@ std::string tune_key(const psgld_ctx *c)
     return buf;
 }
 
-std::mutex g_tune_mutex;
-std::map<std::string, int> g_tune_memo;
+// A tuned schedule: entries per lane group and quads per lane (which sets
+// the lanes per group).
+struct TuneChoice {
+    int entries_per_group = 0;
+    int qpl = 0;
+};
 
-// Entries-per-group remembered for this signature in this process, else in
-// the file named by PSGLD_TUNE_CACHE (lines "<signature> <value>"), else dflt.
-int cached_entries_per_group(const psgld_ctx *c, int dflt)
+std::mutex g_tune_mutex;
+std::map<std::string, TuneChoice> g_tune_memo;
+
+// The choice remembered for this signature in this process, else in the
+// file named by PSGLD_TUNE_CACHE (lines "<signature> <entries per group>
+// <quads per lane>"), else none (entries_per_group 0).
+TuneChoice cached_choice(const psgld_ctx *c)
 {
     const std::string key = tune_key(c);
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_memo.find(key);
     if (it != g_tune_memo.end()) return it->second;
+    TuneChoice found;
     if (const char *path = std::getenv("PSGLD_TUNE_CACHE")) {
         if (FILE *f = std::fopen(path, "r")) {
             char k[256];
-            int v = 0;
-            int found = -1;
-            while (std::fscanf(f, "%255s %d", k, &v) == 2)
-                if (key == k) found = v;
+            int v = 0, q = 0;
+            while (std::fscanf(f, "%255s %d %d", k, &v, &q) == 3)
+                if (key == k && v > 0 && sparse_variant_exists(sparse_lanes_for(c->K, q), q)) found = TuneChoice{v, q};
             std::fclose(f);
-            if (found > 0) {
-                g_tune_memo[key] = found;
-                return found;
-            }
+            if (found.entries_per_group > 0) g_tune_memo[key] = found;
         }
     }
-    return dflt;
+    return found;
 }
 
-void remember_entries_per_group(const psgld_ctx *c, int value)
+void remember_choice(const psgld_ctx *c, TuneChoice value)
 {
     const std::string key = tune_key(c);
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_memo[key] = value;
     if (const char *path = std::getenv("PSGLD_TUNE_CACHE")) {
         if (FILE *f = std::fopen(path, "a")) {
-            std::fprintf(f, "%s %d\n", key.c_str(), value);
+            std::fprintf(f, "%s %d %d\n", key.c_str(), value.entries_per_group, value.qpl);
             std::fclose(f);
         }
     }
+}
+
+// Sets the quads per lane (and so the lanes per group) of the sparse kernels.
+void set_variant(psgld_ctx *c, int qpl)
+{
+    c->qpl = qpl;
+    c->lpg = sparse_lanes_for(c->K, qpl);
 }
 
 // Builds and uploads the part-major layout from training coordinates.
@@ -484,7 +497,11 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
     c->part_visits.assign(B, 0);
     c->pre_r.swap(pre_r);
     c->pre_c.swap(pre_c);
-    c->sched.entries_per_group = cached_entries_per_group(c, c->sched.entries_per_group);
+    const TuneChoice tc = cached_choice(c);
+    if (tc.entries_per_group > 0) {
+        c->sched.entries_per_group = tc.entries_per_group;
+        set_variant(c, tc.qpl);
+    }
     if ((s = upload_schedule(c))) return s;
     c->loaded = true;
     return PSGLD_OK;
@@ -1069,9 +1086,11 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
     if ((s = ensure_device(c))) return s;
     if ((s = build_layout(c, static_cast<int64_t>(row.size()), row.data(), col.data(), val.data()))) return s;
 
-    // dense storage, part-major: values, mask, block table, tiles
+    // dense storage, part-major: values, cell codes, block table, tiles
     const int row_align = dense_row_align(c);
     std::vector<float> dv;
+    std::vector<uint32_t> &dcodes = c->dcodes_host;
+    dcodes.clear();
     std::vector<DenseTile> tiles;
     c->dblock_of.assign(static_cast<size_t>(B) * B, -1);
     c->dblocks_host.clear();
@@ -1098,6 +1117,7 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
             blk.ld = (blk.n + kDenseRowAlign - 1) / kDenseRowAlign * kDenseRowAlign;
             blk.n_sub = dense_sub_tiles(blk.m, row_align);
             blk.v_off = static_cast<int64_t>(dv.size());
+
             blk.first_partial = partial;
             const int32_t wg_cols = kDenseTileCols * blk.n_sub;
             blk.n_tiles = (blk.n + wg_cols - 1) / wg_cols;
@@ -1111,6 +1131,11 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
                     const uint8_t t = mask ? (mask[m] != 0) : 1;
                     dv.push_back(t ? V[m] : 0.f);
                     c->dmask_host.push_back(t);
+                    if (t) {
+                        const size_t cell = dv.size() - 1;
+                        if (dcodes.size() <= cell / 16) dcodes.resize(cell / 16 + 1, 0u);
+                        dcodes[cell / 16] |= uint32_t{kMaskTrain} << (2 * (cell % 16));
+                    }
                 }
                 dv.resize(dv.size() + (blk.ld - blk.n), 0.f);
                 c->dmask_host.resize(c->dmask_host.size() + (blk.ld - blk.n), 0);
@@ -1134,7 +1159,8 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
         if ((s = upload(c, &c->dtiles, tiles))) return s;
         c->dtiles_host = tiles;
         if ((s = upload(c, &c->dval, dv))) return s;
-        if ((s = upload(c, &c->dmask, c->dmask_host))) return s;
+        dcodes.resize((dv.size() + 15) / 16, 0u);
+        if ((s = upload(c, &c->dmask, dcodes))) return s;
         // one slot per tile, each as tall as the tallest padded block
         if ((s = dev_alloc(c, &c->w_partial, static_cast<size_t>(max_partial_slots) * dense_slot_rows(c) * c->Kp)))
             return s;
@@ -1170,8 +1196,12 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     // that covers them
     std::vector<uint8_t> in_dense(n, 0);
     std::vector<std::vector<DenseHeld>> dh(c->dtiles_host.size());
-    std::vector<uint8_t> dmask_dev;
-    if (!c->dblocks_host.empty()) dmask_dev = c->dmask_host;
+    std::vector<uint8_t> held_mark;   // cells of dense blocks seen in this list
+    std::vector<uint32_t> held_codes;  // the blocks' cell codes with these cells marked held-out
+    if (!c->dblocks_host.empty()) {
+        held_mark = c->dmask_host;
+        held_codes = c->dcodes_host;
+    }
     for (int64_t e = 0; e < n; ++e) {
         c->ho_part[e] = part_of(c, row[e], col[e]);
         const int32_t db = c->dblock_of.empty() ? -1
@@ -1181,8 +1211,9 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
             const int32_t i = row[e] - blk.row0, j = col[e] - blk.col0;
             const size_t cell = static_cast<size_t>(blk.v_off) + static_cast<size_t>(i) * blk.ld + j;
             if (c->dmask_host[cell] == kMaskTrain) return c->fail(PSGLD_E_STATE, "held-out cell is also a training entry");
-            if (dmask_dev[cell] == kMaskHeld) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
-            dmask_dev[cell] = kMaskHeld;
+            if (held_mark[cell] == kMaskHeld) return c->fail(PSGLD_E_ARG, "duplicate held-out cell");
+            held_mark[cell] = kMaskHeld;
+            held_codes[cell / 16] |= uint32_t{kMaskHeld} << (2 * (cell % 16));
             in_dense[e] = 1;
             const int32_t wg_cols = kDenseTileCols * blk.n_sub;
             dh[c->dblock_first_tile[db] + j / wg_cols].push_back(DenseHeld{i, j % wg_cols, static_cast<int32_t>(e), 0});
@@ -1217,7 +1248,7 @@ psgld_status psgld_load_heldout(psgld_ctx *c, int64_t n, const int32_t *row, con
     if (!c->dblocks_host.empty()) {
         HIPTRY(c, hipMemcpy(c->dtiles, c->dtiles_host.data(), c->dtiles_host.size() * sizeof(DenseTile),
                             hipMemcpyHostToDevice));
-        HIPTRY(c, hipMemcpy(c->dmask, dmask_dev.data(), dmask_dev.size(), hipMemcpyHostToDevice));
+        HIPTRY(c, hipMemcpy(c->dmask, held_codes.data(), held_codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     // coordinate-block cells: distinct, and disjoint from the training entries
     std::vector<int32_t> rp(static_cast<size_t>(B) * I + 1);
@@ -1610,12 +1641,17 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
         if (candidates[k] < 1) return c->fail(PSGLD_E_ARG, "candidates must be >= 1");
     psgld_status s;
     HIPTRY(c, use_device(c->opt.device));
-    int best = candidates[0];
+    TuneChoice best{candidates[0], c->qpl};
     if (n > 1) {
         if ((s = check_schedule(c, sched))) return s;
         if ((s = sync_and_check(c))) return s;
         if (iters < 1) iters = c->B;
         if ((s = ensure_eps_table(c, sched, c->t, c->t + iters))) return s;
+        // kernel variants: quads per lane 1, 2 or 4 with the lanes that cover
+        // the row, where such a kernel is built
+        std::vector<int> qpls;
+        for (int q : {1, 2, 4})
+            if (sparse_variant_exists(sparse_lanes_for(c->K, q), q)) qpls.push_back(q);
         // trials run on copies of the state, from the context's current t
         const size_t nw = static_cast<size_t>(c->I) * c->Kp + kFactorPad, nh = static_cast<size_t>(c->J) * c->Kp + kFactorPad;
         const int cur0 = c->cur;
@@ -1627,27 +1663,31 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
         HIPTRY(c, hipEventCreate(&e0));
         HIPTRY(c, hipEventCreate(&e1));
         float best_ms = 0.f;
-        for (int32_t k = 0; k < n; ++k) {
-            c->sched.entries_per_group = candidates[k];
-            if ((s = upload_schedule(c))) return s;
-            float ms = 0.f;
-            for (int rep = 0; rep < 2; ++rep) {   // first pass warms up
-                HIPTRY(c, hipMemcpyAsync(c->W[cur0], w0, nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-                HIPTRY(c, hipMemcpyAsync(c->H[cur0], h0, nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-                c->cur = cur0;
-                HIPTRY(c, hipEventRecord(e0, c->stream));
-                for (int32_t it = 0; it < iters; ++it)
-                    HIPTRY(c, enqueue_iteration(c, part_at(c, c->t + it), (cur0 + it) & 1,
-                                                nullptr, static_cast<int32_t>(c->t + it), false, c->stream));
-                HIPTRY(c, hipEventRecord(e1, c->stream));
-                HIPTRY(c, hipEventSynchronize(e1));
-                HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
+        bool first = true;
+        for (int q : qpls)
+            for (int32_t k = 0; k < n; ++k) {
+                set_variant(c, q);
+                c->sched.entries_per_group = candidates[k];
+                if ((s = upload_schedule(c))) return s;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2; ++rep) {   // first pass warms up
+                    HIPTRY(c, hipMemcpyAsync(c->W[cur0], w0, nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+                    HIPTRY(c, hipMemcpyAsync(c->H[cur0], h0, nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+                    c->cur = cur0;
+                    HIPTRY(c, hipEventRecord(e0, c->stream));
+                    for (int32_t it = 0; it < iters; ++it)
+                        HIPTRY(c, enqueue_iteration(c, part_at(c, c->t + it), (cur0 + it) & 1,
+                                                    nullptr, static_cast<int32_t>(c->t + it), false, c->stream));
+                    HIPTRY(c, hipEventRecord(e1, c->stream));
+                    HIPTRY(c, hipEventSynchronize(e1));
+                    HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
+                }
+                if (first || ms < best_ms) {
+                    best_ms = ms;
+                    best = TuneChoice{candidates[k], q};
+                    first = false;
+                }
             }
-            if (k == 0 || ms < best_ms) {
-                best_ms = ms;
-                best = candidates[k];
-            }
-        }
         HIPTRY(c, hipMemcpyAsync(c->W[cur0], w0, nw * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         HIPTRY(c, hipMemcpyAsync(c->H[cur0], h0, nh * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         c->cur = cur0;
@@ -1656,11 +1696,38 @@ psgld_status psgld_tune(psgld_ctx *c, const int32_t *candidates, int32_t n, int3
         (void)hipEventDestroy(e1);
         dev_free(c, w0);
         dev_free(c, h0);
-        remember_entries_per_group(c, best);
+        remember_choice(c, best);
     }
-    c->sched.entries_per_group = best;
+    set_variant(c, best.qpl);
+    c->sched.entries_per_group = best.entries_per_group;
     if ((s = upload_schedule(c))) return s;
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best.entries_per_group;
+    return PSGLD_OK;
+}
+
+psgld_status psgld_set_schedule(psgld_ctx *c, int32_t entries_per_group, int32_t quads_per_lane)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (!c->loaded) return c->fail(PSGLD_E_STATE, "load data first");
+    if (entries_per_group < 1) return c->fail(PSGLD_E_ARG, "entries_per_group must be >= 1");
+    if (quads_per_lane == 0) quads_per_lane = sparse_quads_per_lane(c->K);
+    if (!sparse_variant_exists(sparse_lanes_for(c->K, quads_per_lane), quads_per_lane))
+        return c->fail(PSGLD_E_ARG, "no kernel variant with that many quads per lane for this rank");
+    HIPTRY(c, use_device(c->opt.device));
+    set_variant(c, quads_per_lane);
+    c->sched.entries_per_group = entries_per_group;
+    return upload_schedule(c);
+}
+
+psgld_status psgld_schedule_info(psgld_ctx *c, int32_t *entries_per_group, int32_t *quads_per_lane,
+                                 int32_t *lanes_per_group)
+{
+    if (!c) return PSGLD_E_ARG;
+    c->err.clear();
+    if (entries_per_group) *entries_per_group = c->sched.entries_per_group;
+    if (quads_per_lane) *quads_per_lane = c->qpl;
+    if (lanes_per_group) *lanes_per_group = c->lpg;
     return PSGLD_OK;
 }
 

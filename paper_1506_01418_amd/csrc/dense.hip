@@ -2,7 +2,7 @@
 //
 // For a dense block (rows R_b, columns C_c) of the part, Eq. (8)-(9) need
 //   mu  = W_b H_c                (the block's means, Eq. (13))
-//   E   = mask * (V - mu~) mu~^(beta-2) / phi
+//   E   = train * (V - mu~) mu~^(beta-2) / phi   (train: 1 for training cells)
 //   G_H = W_b^T E                (K x |C_c|: complete per column)
 //   G_W = E H_c^T                (|R_b| x K: summed over the block's columns)
 // A work-group owns up to kDenseSubTiles x 64 columns of one block (fewer
@@ -166,34 +166,34 @@ __device__ __forceinline__ void stage_store(const Stage &st, float *lds, int j0,
     }
 }
 
-// Register staging of the values and mask bytes of a sub-tile's first 64
-// rows: kVQ float4 of values and 8 mask bytes per thread, aligned loads
-// (rows start on 64-byte boundaries), so a wave reads whole 256-byte row
-// pieces.  Cells past the block's rows or its padded width read as missing.
+// Register staging of the values and cell codes of a sub-tile's first 64
+// rows: kVQ float4 of values per thread, aligned loads (rows start on
+// 64-byte boundaries), so a wave reads whole 256-byte row pieces; the first
+// 256 threads each take one 32-bit word (16 cells) of codes.  Cells past the
+// block's rows or its padded width read as missing.
 constexpr int kVQ = 64 * 64 / 4 / kDenseThreads;
-static_assert(64 * 64 == 8 * kDenseThreads, "one 8-byte piece of the mask per thread");
 struct VStage {
     float4 v[kVQ];
-    uint2 mk;
+    uint32_t mk;
 };
 
-__device__ __forceinline__ void vstage_load(VStage &st, const float *V, const uint8_t *M, int ld, int m, int cl,
-                                            int tid)
+__device__ __forceinline__ void vstage_load(VStage &st, const float *V, const uint32_t *M, const DenseBlock &blk,
+                                            int m, int cl, int tid)
 {
+    const int ld = blk.ld;
 #pragma unroll
     for (int u = 0; u < kVQ; ++u) {
         const int f = tid + u * kDenseThreads;
         const int j = f >> 4, c = cl + 4 * (f & 15);
         st.v[u] = (j < m && c < ld) ? load4(V + static_cast<size_t>(j) * ld + c) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    const int j = tid >> 3, c = cl + 8 * (tid & 7);
-    st.mk = (j < m && c < ld) ? *reinterpret_cast<const uint2 *>(M + static_cast<size_t>(j) * ld + c)
-                              : make_uint2(0u, 0u);
+    const int j = tid >> 2, c = cl + 16 * (tid & 3);
+    st.mk = (tid < 256 && j < m && c < ld) ? M[(blk.v_off + static_cast<int64_t>(j) * ld + c) >> 4] : 0u;
 }
 
 // Values into rows 0 .. min(64, rows) - 1 of sV (row stride `stride`; sV
-// has `rows` rows), mask bytes into sM (64 x 64, row stride 64).
-__device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int stride, int rows, uint8_t *sM,
+// has `rows` rows), codes into sM (64 rows x 4 words of 16 cells).
+__device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int stride, int rows, uint32_t *sM,
                                              int tid)
 {
 #pragma unroll
@@ -206,7 +206,7 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
         d[2] = st.v[u].z;
         d[3] = st.v[u].w;
     }
-    *reinterpret_cast<uint2 *>(sM + (tid >> 3) * 64 + 8 * (tid & 7)) = st.mk;
+    if (tid < 256) sM[tid] = st.mk;
 }
 
 // One work-group: up to kDenseSubTiles consecutive 64-column sub-tiles of
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     float *sW = lds;                   // [MT][KS+1]   W_b
     float *sH = sW + MT * sw;          // [NT][KS+1]   H columns of the sub-tile
     float *sE = sH + kNT * sw;         // [MT][NT+1]   values of the sub-tile, then E
-    uint8_t *sM = reinterpret_cast<uint8_t *>(sE + MT * se);   // [64][64] mask bytes of rows 0..63
+    uint32_t *sM = reinterpret_cast<uint32_t *>(sE + MT * se);   // [64][4] cell codes of rows 0..63
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, h4 = lane >> 4;
     const int wq = wave & 3, ch = wave >> 2;
@@ -250,14 +250,15 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     if (MT > kNT) stage_store(ws1, sW, kNT, MT, sw, KS, tid);
 
     const float *V = a.val + blk.v_off;
-    const uint8_t *M = a.mask + blk.v_off;
+    const uint32_t *M = a.mask;
+    const uint32_t *Mb = M + (blk.v_off >> 4);   // the block's code words
     const int ld = blk.ld;
     // FP32 operands: values and mask bytes of rows 0..63 prefetched one
     // sub-tile ahead; BF16 operands need those registers for the operand
     // conversions, and read the values in place before each product
     constexpr bool kStageV = !BF16;
     VStage vs;
-    if constexpr (kStageV) vstage_load(vs, V, M, ld, m, tile.col, tid);
+    if constexpr (kStageV) vstage_load(vs, V, M, blk, m, tile.col, tid);
     const int kt = wq;                            // this wave's k-tile in G_H and G_W
     const bool has_kt = kt * 16 < KS;
     const int n_it = MT / 16;                     // 16-row tiles of the block
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         if constexpr (kStageV) vstage_store(vs, sE, se, MT, sM, tid);
         if (sub + 1 < blk.n_sub && cl + kNT < blk.n) {
             stage_load(hs, Hold, col0 + kNT, min(kNT, blk.n - cl - kNT), Kp, tid);
-            if constexpr (kStageV) vstage_load(vs, V, M, ld, m, cl + kNT, tid);
+            if constexpr (kStageV) vstage_load(vs, V, M, blk, m, cl + kNT, tid);
         }
         __syncthreads();
 
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                     for (int r = 0; r < 4; ++r) {
                         const int i = it * 16 + 4 * h4 + r, j = (2 * ch + t) * 16 + c16;
                         vv[t][r] = sE[i * se + j];
-                        mm[t][r] = sM[i * 64 + j];
+                        mm[t][r] = (sM[4 * i + 2 * ch + t] >> (2 * c16)) & 3u;   // j = 16 (2 ch + t) + c16
                     }
             } else {
 #pragma unroll
@@ -306,7 +307,10 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                         const int j = min((2 * ch + t) * 16 + c16, ncol - 1);
                         const size_t cell = static_cast<size_t>(i) * ld + cl + j;
                         vv[t][r] = V[cell];
-                        mm[t][r] = M[cell];
+                        // v_off, ld and cl are multiples of 16: the cell's code
+                        // sits at bits 2 c16 of its word (a clamped cell
+                        // reads another code, masked as outside)
+                        mm[t][r] = (Mb[cell >> 4] >> (2 * c16)) & 3u;
                     }
             }
             v4f acc[2] = {};
@@ -440,7 +444,7 @@ size_t dense_lds_bytes(int max_m, int KS)
     const int MT = (max_m + 31) / 32 * 32;   // at least the padded height of any block
     return sizeof(float) * (static_cast<size_t>(MT) * (KS + 1) + static_cast<size_t>(kNT) * (KS + 1) +
                             static_cast<size_t>(MT) * (kNT + 1)) +
-           64 * kNT;                             // mask bytes of rows 0..63
+           64 * 16;                              // cell codes of rows 0..63
 }
 
 hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max_m, hipStream_t stream)

@@ -193,6 +193,8 @@ hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lanes_per_gr
                               hipStream_t stream);
 int sparse_threads_per_group(int K);
 int sparse_quads_per_lane(int K);
+int sparse_lanes_for(int K, int qpl);
+bool sparse_variant_exists(int lpg, int qpl);
 int sparse_block_threads();
 
 // Tunable shape of the sparse schedule (chosen per context by psgld_tune).
@@ -224,13 +226,14 @@ constexpr int kDenseMaxRows = 128;   // dense blocks have at most this many rows
 constexpr int kDenseMaxK = 64;       // and rank at most this
 
 // A dense block of a part: rows [row0, row0 + m), columns [col0, col0 + n);
-// its values and mask bytes are stored row-major at v_off with row stride
-// ld = n rounded up to kDenseRowAlign cells (the padding cells are missing:
-// value 0, mask 0), so every row starts on a 64-byte boundary of the values
-// and a 16-byte boundary of the mask.  Each of its n_tiles work-groups
-// takes n_sub consecutive 64-column sub-tiles (fewer for taller blocks, so
-// every work-group has about the same work); their W partials occupy slots
-// first_partial .. + n_tiles.
+// its values are stored row-major at v_off with row stride ld = n rounded up
+// to kDenseRowAlign cells (padding cells hold 0), so every row starts on a
+// 64-byte boundary.  Every stored cell also has a 2-bit code (0 missing, 1
+// training, 2 held-out) in an array parallel to the values, 16 cells per
+// 32-bit word: cell c is bits 2 (c mod 16) of word c / 16.  Each of its
+// n_tiles work-groups takes n_sub consecutive 64-column sub-tiles (fewer for
+// taller blocks, so every work-group has about the same work); their W
+// partials occupy slots first_partial .. + n_tiles.
 constexpr int kDenseRowAlign = 16;
 struct DenseBlock {
     int32_t row0, m, col0, n;
@@ -238,6 +241,12 @@ struct DenseBlock {
     int32_t first_partial, n_tiles;
     int32_t ld, n_sub;
 };
+
+// Code of stored cell c of the dense blocks: 0 missing, 1 training, 2 held-out.
+__host__ __device__ __forceinline__ uint32_t dense_code(const uint32_t *codes, int64_t c)
+{
+    return (codes[c >> 4] >> (2 * (c & 15))) & 3u;
+}
 
 // One work-group's share of a block: columns [col, col + n_sub * 64)
 // of part block `block`; its W partial goes to slot `partial`; the held-out
@@ -249,7 +258,7 @@ struct DenseTile {
     int32_t ho[kDenseSubTiles + 1];
 };
 
-// Dense-block mask byte: 0 missing, 1 training cell, 2 held-out cell.
+// Dense-block cell codes: 0 missing, 1 training cell, 2 held-out cell.
 constexpr uint8_t kMaskTrain = 1;
 constexpr uint8_t kMaskHeld = 2;
 
@@ -268,7 +277,7 @@ struct DenseIterArgs {
     const DenseTile *tiles;     // the part's tiles
     int32_t n_tiles;
     const float *val;
-    const uint8_t *mask;
+    const uint32_t *mask;       // 2-bit cell codes
     float *w_partial;           // slot_rows x Kp floats per tile
     int32_t slot_rows;          // rows of every W partial slot (the largest padded block height)
     int32_t row_align;          // block heights are padded to this (16 FP32, 32 BF16)
@@ -294,7 +303,7 @@ hipError_t dense_prepare(int max_m, int KS);
 size_t dense_lds_bytes(int max_m, int KS);
 // FP64 log-likelihood partials of all dense blocks' training cells.
 hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
-                               const float *val, const uint8_t *mask, int K, int Kp, double beta, double phi,
+                               const float *val, const uint32_t *mask, int K, int Kp, double beta, double phi,
                                double mu_floor, double *partials, int per_block, hipStream_t stream);
 
 hipError_t launch_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
 
 // Same for the training cells of dense blocks: blockIdx.y is the block.
 __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
-    const float *W, const float *Hs, const DenseBlock *blocks, const float *val, const uint8_t *mask, int K,
+    const float *W, const float *Hs, const DenseBlock *blocks, const float *val, const uint32_t *mask, int K,
     int Kp, double beta, double phi, double mu_floor, double *partials, int per_block)
 {
     __shared__ double red[kLLThreads];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
          e += static_cast<int64_t>(per_block) * kLLThreads) {
         const int i = static_cast<int>(e / blk.n), j = static_cast<int>(e % blk.n);
         const int64_t cell = blk.v_off + static_cast<int64_t>(i) * blk.ld + j;
-        if (mask[cell] != kMaskTrain) continue;
+        if (dense_code(mask, cell) != kMaskTrain) continue;
         const float4 *w = reinterpret_cast<const float4 *>(W + static_cast<size_t>(blk.row0 + i) * Kp);
         const float4 *h = reinterpret_cast<const float4 *>(Hs + static_cast<size_t>(blk.col0 + j) * Kp);
         double mu = 0.0;
@@ -180,7 +180,7 @@ hipError_t launch_loglik(const float *W, const float *Hs, const int32_t *row_of_
 }
 
 hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
-                               const float *val, const uint8_t *mask, int K, int Kp, double beta, double phi,
+                               const float *val, const uint32_t *mask, int K, int Kp, double beta, double phi,
                                double mu_floor, double *partials, int per_block, hipStream_t stream)
 {
     if (n_blocks == 0) return hipSuccess;

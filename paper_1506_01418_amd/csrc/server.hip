@@ -51,7 +51,12 @@ struct Job {
 int64_t estimate_bytes(const psgld_job &j)
 {
     const int64_t I = j.I, J = j.J, B = j.B, Kp = padded_rank(j.K);
-    const int64_t Q = sparse_block_threads() / sparse_threads_per_group(j.K);
+    // the most groups per work-group any kernel variant of this rank uses
+    // (a tuned variant remembered for the shape may be applied at load)
+    int64_t Q = sparse_block_threads() / sparse_threads_per_group(j.K);
+    for (int q : {1, 2, 4})
+        if (sparse_variant_exists(sparse_lanes_for(j.K, q), q))
+            Q = std::max<int64_t>(Q, sparse_block_threads() / sparse_lanes_for(j.K, q));
     int64_t qlog = 0;
     while ((int64_t{1} << qlog) < Q) ++qlog;
     int64_t nnz = j.nnz;
@@ -75,7 +80,8 @@ int64_t estimate_bytes(const psgld_job &j)
     b += 8 * cap;                                                  // step-size table
     b += 4 * (B * I + 1) + 32 * j.n_heldout;                       // held-out offsets, cells, sums
     if (!j.row) {
-        b += 5 * (I * J + (kDenseRowAlign - 1) * I * B);           // dense values and mask, rows padded
+        b += 4 * (I * J + (kDenseRowAlign - 1) * I * B);           // dense values, rows padded
+        b += (I * J + (kDenseRowAlign - 1) * I * B) / 4 + 4;        // 2-bit cell codes
         b += (J / 128 + B + 1) * int64_t{kDenseMaxRows} * Kp * 4;  // W partials
         b += (B * B + 1) * 64 + (J / 128 + B + 1) * B * 32;        // block and tile lists
     }

@@ -651,14 +651,27 @@ int sparse_quads_per_lane(int K)
     return nq <= 4 ? 1 : nq <= 16 ? 2 : 4;
 }
 
-// Lanes per item group: the smallest power of two covering the quads.
-int sparse_threads_per_group(int K)
+// Lanes per item group for qpl quads per lane: the smallest power of two
+// covering the quads.
+int sparse_lanes_for(int K, int qpl)
 {
-    const int qpl = sparse_quads_per_lane(K);
     const int need = ((K + 3) / 4 + qpl - 1) / qpl;
     int lpg = 1;
     while (lpg < need) lpg *= 2;
     return lpg;
+}
+
+int sparse_threads_per_group(int K) { return sparse_lanes_for(K, sparse_quads_per_lane(K)); }
+
+// The (lanes per group, quads per lane) pairs the kernels are built for.
+bool sparse_variant_exists(int lpg, int qpl)
+{
+    switch (qpl) {
+    case 1: return lpg == 1 || lpg == 2 || lpg == 4 || lpg == 8;
+    case 2: return lpg == 4 || lpg == 8 || lpg == 16 || lpg == 32;
+    case 4: return lpg == 4 || lpg == 8 || lpg == 16;
+    default: return false;
+    }
 }
 
 hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, int qpl, hipStream_t stream)
@@ -669,11 +682,13 @@ hipError_t launch_sparse_batch(const BatchArgs &b, int lik, int lpg, int qpl, hi
         case 1: return launch_batch_lpg<1, 1>(b, lik, stream);
         case 2: return launch_batch_lpg<2, 1>(b, lik, stream);
         case 4: return launch_batch_lpg<4, 1>(b, lik, stream);
+        case 8: return launch_batch_lpg<8, 1>(b, lik, stream);
         default: return hipErrorInvalidValue;
         }
     }
     if (qpl == 4) {
         switch (lpg) {
+        case 4: return launch_batch_lpg<4, 4>(b, lik, stream);
         case 8: return launch_batch_lpg<8, 4>(b, lik, stream);
         case 16: return launch_batch_lpg<16, 4>(b, lik, stream);
         default: return hipErrorInvalidValue;
@@ -700,11 +715,13 @@ hipError_t launch_sparse_persistent(const BatchArgs &b, int n_iter, int lik, int
         case 1: return launch_persistent_lpg<1, 1>(b, n_iter, lik, grid, barrier, stream);
         case 2: return launch_persistent_lpg<2, 1>(b, n_iter, lik, grid, barrier, stream);
         case 4: return launch_persistent_lpg<4, 1>(b, n_iter, lik, grid, barrier, stream);
+        case 8: return launch_persistent_lpg<8, 1>(b, n_iter, lik, grid, barrier, stream);
         default: return hipErrorInvalidValue;
         }
     }
     if (qpl == 4) {
         switch (lpg) {
+        case 4: return launch_persistent_lpg<4, 4>(b, n_iter, lik, grid, barrier, stream);
         case 8: return launch_persistent_lpg<8, 4>(b, n_iter, lik, grid, barrier, stream);
         case 16: return launch_persistent_lpg<16, 4>(b, n_iter, lik, grid, barrier, stream);
         default: return hipErrorInvalidValue;
@@ -746,11 +763,13 @@ hipError_t launch_sparse_iter(const SparseIterArgs &a, int lik, int lpg, int qpl
         case 1: return launch_lpg<1, 1>(a, lik, stream);
         case 2: return launch_lpg<2, 1>(a, lik, stream);
         case 4: return launch_lpg<4, 1>(a, lik, stream);
+        case 8: return launch_lpg<8, 1>(a, lik, stream);
         default: return hipErrorInvalidValue;
         }
     }
     if (qpl == 4) {
         switch (lpg) {
+        case 4: return launch_lpg<4, 4>(a, lik, stream);
         case 8: return launch_lpg<8, 4>(a, lik, stream);
         case 16: return launch_lpg<16, 4>(a, lik, stream);
         default: return hipErrorInvalidValue;

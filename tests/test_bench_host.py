@@ -42,10 +42,10 @@ def test_algorithmic_cost_counts_cells_entries_and_extras():
     assert list(cells) == [256 * 4096 // 4] * 4 and not entries.any()
     ho_p = np.array([7, 0, 0, 0])
     factors = 8 * (wl.I + wl.J) * wl.K
-    assert bench.algorithmic_cost(wl, cells, entries, ho_p, 0, 0) == (5 * cells[0] + factors, 6 * wl.K * cells[0])
+    assert bench.algorithmic_cost(wl, cells, entries, ho_p, 0, 0) == (4.125 * cells[0] + factors, 6 * wl.K * cells[0])
     kept = bench.algorithmic_cost(wl, cells, entries, ho_p, 15, 0)[0]
-    assert kept == 5 * cells[0] + factors + 16 * 7 + 32 * (wl.I + wl.J) * wl.K
-    assert bench.algorithmic_cost(wl, cells, entries, ho_p, 16, 0)[0] == 5 * cells[0] + factors + 16 * 7
+    assert kept == 4.125 * cells[0] + factors + 16 * 7 + 32 * (wl.I + wl.J) * wl.K
+    assert bench.algorithmic_cost(wl, cells, entries, ho_p, 16, 0)[0] == 4.125 * cells[0] + factors + 16 * 7
     # the same matrix in 128-column blocks: every training entry as coordinates
     wl = workloads.dense_tweedie(I=256, J=4096, B=32, name="t")
     dense, cnt, rows, cols = bench.block_placement(wl)

@@ -258,28 +258,31 @@ def test_tune_keeps_chain_and_is_reproducible():
     same bits.  Every candidate schedule stays within the parity bound."""
     wl = CASES["gauss_K50_zipf"]()
     a = pkg.PSGLD.from_workload(wl)
-    a.tune(wl.eps_a, candidates=(64,))
+    a.set_schedule(64)
     a.step(3, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     before = a.factors()
     chosen = a.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=(8, 64), iters=4)
     assert chosen in (8, 64)
+    epg, qpl, lpg = a.schedule_info()
+    assert epg == chosen and qpl in (2, 4) and lpg == {2: 8, 4: 4}[qpl]   # K = 50: 13 quads
     after = a.factors()
     assert all(np.array_equal(x, y) for x, y in zip(before, after)) and a.iteration() == 3
     a.step(5, wl.eps_a, wl.eps_t0, wl.eps_gamma)
-    b = pkg.PSGLD.from_workload(wl)   # loads with the value remembered for this shape
-    b.tune(wl.eps_a, candidates=(64,))
+    b = pkg.PSGLD.from_workload(wl)   # loads with the choice remembered for this shape
+    assert b.schedule_info() == (epg, qpl, lpg)
+    b.set_schedule(64)
     b.step(3, wl.eps_a, wl.eps_t0, wl.eps_gamma)
-    b.tune(wl.eps_a, candidates=(chosen,))
+    b.set_schedule(epg, qpl)
     b.step(5, wl.eps_a, wl.eps_t0, wl.eps_gamma)
     assert all(np.array_equal(x, y) for x, y in zip(a.factors(), b.factors()))
     a.close()
     b.close()
-    for L in (1, 8, 200):
+    for L, q in ((1, 2), (8, 4), (200, 2), (200, 4)):
         s = pkg.PSGLD.from_workload(wl)
-        s.tune(wl.eps_a, candidates=(L,))
+        s.set_schedule(L, q)
         err, _ = step_parity(wl, 2, sampler=s)
         s.close()
-        assert err <= TOL_FP32, (L, err)
+        assert err <= TOL_FP32, (L, q, err)
 
 
 def test_nonfinite_is_reported():
@@ -313,3 +316,18 @@ def test_state_errors():
     with pytest.raises(pkg.PsgldError, match="duplicate"):
         d.load_coo([0, 0], [1, 1], [1.0, 2.0])
     d.close()
+
+
+@pytest.mark.parametrize("K,qpl", [(20, 1), (20, 2), (50, 2), (50, 4), (100, 2), (100, 4), (200, 2), (200, 4)])
+def test_every_kernel_variant_step_parity(K, qpl):
+    """Each (quads per lane, lanes per group) kernel the tuner may choose for
+    a rank steps within the parity bound, before and after burn-in."""
+    wl = workloads.random_sparse(900, 700, 40_000, K, 4, beta=2.0, phi=0.5, zipf_a=1.0,
+                                 data_seed=40 + K, chain_seed=41 + K, burn_in=3, thin=2)
+    s = pkg.PSGLD.from_workload(wl)
+    s.set_schedule(32, qpl)
+    assert s.schedule_info()[1] == qpl
+    err0, _ = step_parity(wl, 0, sampler=s)
+    err1, _ = step_parity(wl, 4, sampler=s)
+    s.close()
+    assert err0 <= TOL_FP32 and err1 <= TOL_FP32, (K, qpl, err0, err1)

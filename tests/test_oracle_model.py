@@ -464,3 +464,29 @@ def test_random_order_steps_use_the_drawn_part():
             ch.run(1)
             inside = (rp[row[e]] + p) % 4 == cp[col[e]]
             assert (not np.array_equal(ch.W, base.W)) == inside, (t, e)
+
+
+# ------------------------------------------------------------------- P9
+def test_results_do_not_depend_on_the_thread_count():
+    """The oracle sums each block of a part on one thread, in (i, j) order,
+    and steps rows and columns independently, so a run on one thread and on
+    several gives the same bits (factors, moments, held-out sums, bounds).
+    The problem is large enough that every parallel loop does fork."""
+    wl = workloads.random_sparse(4000, 2500, 60_000, 16, 5, beta=1.0, prior="exponential", mirror=True,
+                                 zipf_a=1.0, data_seed=61, chain_seed=62, burn_in=2, thin=2)
+    threads0 = oracle.threads()
+    runs = []
+    try:
+        for n in (1, 3, 8):
+            oracle.threads(n)
+            assert oracle.threads() == n
+            cfg = oracle.Config(**wl.fit_kwargs())
+            ch = oracle.Chain(cfg, wl.row, wl.col, wl.val, wl.W0, wl.H0, wl.hrow, wl.hcol)
+            ch.run(6)
+            bW, bH = ch.run(1, bounds=True)
+            runs.append((ch.W, ch.H, ch.sumW, ch.sumH2, ch.ho_sum, bW, bH))
+    finally:
+        oracle.threads(threads0)
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
