@@ -215,7 +215,7 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
 // k-tile wq over column half ch, in G_W k-tile wq over the 16-row tiles ch,
 // ch + 2, ... (K <= 64).  The next
 // sub-tile's H columns are loaded into registers while the current one is
-// computed, and so are the values and mask bytes of its first 64 rows (rows
+// computed, and so are the values and cell codes of its first 64 rows (rows
 // past 64 are loaded before their row tile's product), so no product waits
 // on a round trip to memory it could have started earlier.  G_W accumulates
 // in registers over the sub-tiles and is written once, as this work-group's
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     const uint32_t *M = a.mask;
     const uint32_t *Mb = M + (blk.v_off >> 4);   // the block's code words
     const int ld = blk.ld;
-    // FP32 operands: values and mask bytes of rows 0..63 prefetched one
+    // FP32 operands: values and cell codes of rows 0..63 prefetched one
     // sub-tile ahead; BF16 operands need those registers for the operand
     // conversions, and read the values in place before each product
     constexpr bool kStageV = !BF16;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         __syncthreads();
 
         // mu = W_b H^T (MT x 64) and E, one 16-row tile at a time; values and
-        // mask bytes of rows 0..63 come from LDS, those of later rows
+        // cell codes of rows 0..63 come from LDS, those of later rows
         // (clamped into the block, masked after) are requested before the
         // tile's product
         for (int it = wq; it < n_it; it += 4) {
