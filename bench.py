@@ -47,7 +47,10 @@ METRIC = "observed-entry SGLD updates/s at matched held-out RMSE; served-job p50
 PAPER_UPDATES_PER_S = {"paper_poisson_1024": 10_000 * 1024 * 1024 / 32 / 15.0,
                        "paper_spectrum_256": 10_000 * 256 * 256 / 8 / 3.5}
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "bf16v": 2500.0}
+# Stored bytes of a dense cell's training value per precision (bf16v: the
+# values themselves stored in BF16).
+VALUE_BYTES = {"f32": 4, "bf16": 4, "bf16v": 2}
 
 
 class HipEvents:
@@ -118,16 +121,17 @@ def part_work(wl, dense, cnt, rows, cols):
     return cells, entries
 
 
-def algorithmic_cost(wl, cells_p, entries_p, ho_p, t, p):
+def algorithmic_cost(wl, cells_p, entries_p, ho_p, t, p, value_bytes=4):
     """(bytes, flops) one iteration must move and compute at minimum: each
     training entry of the part's coordinate blocks read once (4-byte index +
-    4-byte value), each cell of its dense blocks read once (FP32 value + one
-    bit of training mask), every factor element read and written once in
+    4-byte value), each cell of its dense blocks read once (its value in the
+    stored precision, value_bytes, + one bit of training mask), every factor
+    element read and written once in
     FP32, the FP64 sums of x and x^2 read and written at kept iterations, one
     FP64 read-modify-write per held-out cell of the part after burn-in; 6K
     flops per dense cell for mu = W H, G_H = W^T E and G_W = E H^T.  p is the
     part of iteration t."""
-    b = 4.125 * cells_p[p] + 8 * entries_p[p] + 8 * (wl.I + wl.J) * wl.K
+    b = (value_bytes + 0.125) * cells_p[p] + 8 * entries_p[p] + 8 * (wl.I + wl.J) * wl.K
     if t >= wl.burn_in:
         b += 16 * ho_p[p]
         if (t - wl.burn_in) % wl.thin == 0:
@@ -332,8 +336,9 @@ def main():
                          "many iterations against the sampler's time (0: off)")
     ap.add_argument("--cpu-iters", type=int, default=0, help="exact oracle iterations instead (0: by time)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precision", choices=["f32", "bf16"], default="f32",
-                    help="operand precision of the dense-block kernels")
+    ap.add_argument("--precision", choices=["f32", "bf16", "bf16v"], default="f32",
+                    help="dense-block kernels: FP32 operands, BF16 operands, or BF16 operands with the "
+                         "training values also stored in BF16")
     ap.add_argument("--entries-per-group", type=int, default=0,
                     help="fix the sparse schedule's entries per group instead of tuning it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -373,7 +378,7 @@ def main():
 
     ev = HipEvents()
     dense = wl.dense is not None and not args.coo
-    prec = pkg.PSGLD_BF16_DENSE if args.precision == "bf16" else pkg.PSGLD_FP32
+    prec = {"f32": pkg.PSGLD_FP32, "bf16": pkg.PSGLD_BF16_DENSE, "bf16v": pkg.PSGLD_BF16_DENSE_VALUES}[args.precision]
     t_load = time.perf_counter()
     pieces = {}
     if args.balanced and not dense:
@@ -449,7 +454,8 @@ def main():
     post = durs[min(args.steps, wl.burn_in):]
     print(f"[bench] launch average before burn-in {pre.mean() * 1e3:.2f} us"
           + (f", after {post.mean() * 1e3:.2f} us" if len(post) else ""), file=sys.stderr, flush=True)
-    bf = np.array([algorithmic_cost(wl, cells_p, entries_p, ho_p, t, parts[t]) for t in range(args.steps)],
+    vb = VALUE_BYTES[args.precision] if dense else 4
+    bf = np.array([algorithmic_cost(wl, cells_p, entries_p, ho_p, t, parts[t], vb) for t in range(args.steps)],
                   dtype=np.float64)
     alg, flops = bf[:, 0], bf[:, 1]
     t_hbm = alg.mean() / (HBM_PEAK_GBS * 1e9)
@@ -541,7 +547,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed_ms / args.steps,
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": value / PAPER_UPDATES_PER_S[wl.name] if wl.name in PAPER_UPDATES_PER_S else None,
-        "dtype": "bf16+f32" if runs_dense and args.precision == "bf16" else "f32",
+        "dtype": "bf16+f32" if runs_dense and args.precision in ("bf16", "bf16v") else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "I": wl.I, "J": wl.J, "nnz_train": wl.nnz,
                    "nnz_heldout": int(len(wl.hrow)), "K": wl.K, "B": wl.B, "beta": wl.beta,

@@ -85,7 +85,15 @@ typedef struct {
     double gamma;
 } psgld_eps_schedule;
 
-enum { PSGLD_FP32 = 0, PSGLD_BF16_DENSE = 1 };
+/* Precision of the dense-block kernels (coordinate entries are always FP32).
+ * PSGLD_BF16_DENSE: the three products of Eq. (8)-(9) on a dense block take
+ * W, H and E rounded to BF16 (nearest even), accumulating in FP32.
+ * PSGLD_BF16_DENSE_VALUES: the same, and the dense blocks' training values
+ * are also stored in BF16, rounded to nearest even once when loaded: the
+ * chain then samples the posterior of those rounded values (relative change
+ * at most 2^-9 per value; integers up to 256 are unchanged), and an
+ * iteration reads 2 instead of 4 bytes per cell. */
+enum { PSGLD_FP32 = 0, PSGLD_BF16_DENSE = 1, PSGLD_BF16_DENSE_VALUES = 2 };
 /* Part order: cyclic, p_t = t mod B (Section 4.2.1), or drawn at every
  * iteration with probability |part| / N (Condition 2) from the Philox stream
  * PART = 4: counter (0, 0, t, 4), u = (2 (r0 >> 9) + 1) 2^-24, part = the
@@ -102,7 +110,7 @@ typedef struct {
     uint64_t seed;            /* Philox key of the Langevin noise */
     int64_t burn_in;          /* moments and held-out sums start at t >= burn_in */
     int32_t thin;             /* moments kept at t - burn_in = 0, thin, 2 thin, ... */
-    int32_t precision;        /* PSGLD_FP32 or PSGLD_BF16_DENSE (dense blocks only) */
+    int32_t precision;        /* PSGLD_FP32, PSGLD_BF16_DENSE or PSGLD_BF16_DENSE_VALUES (dense blocks only) */
     double dense_threshold;   /* blocks denser than this use the dense kernel */
     double mu_floor;          /* floor of the Tweedie mean when beta < 2 */
     const int32_t *row_piece; /* optional, length I: piece of each row; NULL = contiguous split */

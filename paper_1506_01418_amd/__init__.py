@@ -32,6 +32,7 @@ PSGLD_PRIOR_EXPONENTIAL = 0
 PSGLD_PRIOR_GAUSSIAN = 1
 PSGLD_FP32 = 0
 PSGLD_BF16_DENSE = 1
+PSGLD_BF16_DENSE_VALUES = 2
 PSGLD_TEST_NOISE_OFF = 1
 PSGLD_TEST_FREEZE_W = 2
 PSGLD_TEST_FREEZE_H = 4

@@ -113,6 +113,7 @@ struct psgld_ctx {
     DenseBlock *dblocks = nullptr;
     DenseTile *dtiles = nullptr;
     float *dval = nullptr;
+    uint16_t *dval16 = nullptr;             // the values in BF16 (PSGLD_BF16_DENSE_VALUES; dval is then null)
     uint32_t *dmask = nullptr;              // 2-bit cell codes of the dense blocks
     std::vector<uint32_t> dcodes_host;      // their host copy
     float *w_partial = nullptr;
@@ -509,9 +510,21 @@ psgld_status build_layout(psgld_ctx *c, int64_t nnz, const int32_t *row, const i
 
 int32_t dense_slot_rows(const psgld_ctx *c) { return (c->dense_max_m + 31) / 32 * 32; }
 
+// Dense products on BF16 operands (both BF16 precisions).
+bool bf16_operands(const psgld_ctx *c) { return c->opt.precision != PSGLD_FP32; }
+
+// FP32 -> BF16, rounded to nearest even (values are finite: checked on load).
+uint16_t bf16_round(float v)
+{
+    uint32_t u;
+    std::memcpy(&u, &v, sizeof u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
 // Rows of a dense block's MFMA tiles are padded to this: the k-depth of one
 // MFMA step over rows (4 for FP32 operands, 32 for BF16), rounded to 16.
-int dense_row_align(const psgld_ctx *c) { return c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16; }
+int dense_row_align(const psgld_ctx *c) { return bf16_operands(c) ? 32 : 16; }
 
 // Sub-tiles per work-group for a block of m rows: the four waves of a
 // work-group share a sub-tile's 16-row tiles, so a block of up to 64 (padded)
@@ -691,6 +704,7 @@ hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *cl
         d.tiles = c->dtiles + c->dtile_off[p];
         d.n_tiles = static_cast<int32_t>(c->dtile_cnt[p]);
         d.val = c->dval;
+        d.val16 = c->dval16;
         d.mask = c->dmask;
         d.w_partial = c->w_partial;
         d.slot_rows = dense_slot_rows(c);
@@ -718,7 +732,7 @@ hipError_t enqueue_iteration(psgld_ctx *c, int32_t p, int cur, const int32_t *cl
         d.heldout = c->dheld;
         d.ho_sum = c->ho_sum;
         d.nonfinite = c->nonfinite;
-        e = launch_dense_iter(d, c->lik_kind, c->opt.precision == PSGLD_BF16_DENSE, c->dense_max_m, stream);
+        e = launch_dense_iter(d, c->lik_kind, bf16_operands(c), c->dense_max_m, stream);
     }
     return e;
 }
@@ -952,7 +966,8 @@ psgld_status psgld_create(int64_t I, int64_t J, int32_t K, int32_t B, const psgl
     if (o.thin < 1) return bad("thin must be >= 1");
     if (o.burn_in < 0) return bad("burn_in must be >= 0");
     if (!(o.mu_floor > 0.0)) return bad("mu_floor must be > 0");
-    if (o.precision != PSGLD_FP32 && o.precision != PSGLD_BF16_DENSE) return bad("unknown precision");
+    if (o.precision != PSGLD_FP32 && o.precision != PSGLD_BF16_DENSE && o.precision != PSGLD_BF16_DENSE_VALUES)
+        return bad("unknown precision");
     if (o.device < 0) return bad("device must be >= 0");
     if (o.part_order != PSGLD_PART_CYCLIC && o.part_order != PSGLD_PART_RANDOM) return bad("unknown part order");
     if (o.dense_min_cols < 1) return bad("dense_min_cols must be >= 1");
@@ -1152,13 +1167,19 @@ psgld_status psgld_load_dense(psgld_ctx *c, const float *V, const uint8_t *mask)
         max_partial_slots = std::max<int64_t>(max_partial_slots, partial);
     }
     if (!c->dblocks_host.empty()) {
-        const int align = c->opt.precision == PSGLD_BF16_DENSE ? 32 : 16;
+        const int align = bf16_operands(c) ? 32 : 16;
         c->KS = (c->K + align - 1) / align * align;
         HIPTRY(c, dense_prepare(c->dense_max_m, c->KS));
         if ((s = upload(c, &c->dblocks, c->dblocks_host))) return s;
         if ((s = upload(c, &c->dtiles, tiles))) return s;
         c->dtiles_host = tiles;
-        if ((s = upload(c, &c->dval, dv))) return s;
+        if (c->opt.precision == PSGLD_BF16_DENSE_VALUES) {
+            std::vector<uint16_t> dv16(dv.size());
+            for (size_t k = 0; k < dv.size(); ++k) dv16[k] = bf16_round(dv[k]);
+            if ((s = upload(c, &c->dval16, dv16))) return s;
+        } else if ((s = upload(c, &c->dval, dv))) {
+            return s;
+        }
         dcodes.resize((dv.size() + 15) / 16, 0u);
         if ((s = upload(c, &c->dmask, dcodes))) return s;
         // one slot per tile, each as tall as the tallest padded block
@@ -1841,7 +1862,7 @@ psgld_status psgld_log_likelihood(psgld_ctx *c, double *ll)
     HIPTRY(c, launch_loglik(c->W[c->cur], c->H[c->cur], c->row_of_entry, c->ent_r, c->nnz_sparse, c->K, c->Kp,
                             c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials, c->ll_blocks, c->stream));
     const int nd = static_cast<int>(c->dblocks_host.size());
-    HIPTRY(c, launch_dense_loglik(c->W[c->cur], c->H[c->cur], c->dblocks, nd, c->dval, c->dmask, c->K, c->Kp,
+    HIPTRY(c, launch_dense_loglik(c->W[c->cur], c->H[c->cur], c->dblocks, nd, c->dval, c->dval16, c->dmask, c->K, c->Kp,
                                   c->lik.beta, c->lik.phi, c->opt.mu_floor, c->ll_partials + c->ll_blocks,
                                   kDenseLLPerBlock, c->stream));
     HIPTRY(c, launch_sum_in_order(c->ll_partials, c->ll_blocks + nd * kDenseLLPerBlock, c->ll_out, c->stream));

@@ -220,7 +220,7 @@ __device__ __forceinline__ void vstage_store(const VStage &st, float *sV, int st
 // on a round trip to memory it could have started earlier.  G_W accumulates
 // in registers over the sub-tiles and is written once, as this work-group's
 // partial.
-template <bool BF16, int LIK>
+template <bool BF16, int LIK, bool VAL16>
 __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void dense_tile_kernel(DenseIterArgs a)
 {
     extern __shared__ float lds[];
@@ -249,7 +249,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     stage_store(ws0, sW, 0, MT, sw, KS, tid);
     if (MT > kNT) stage_store(ws1, sW, kNT, MT, sw, KS, tid);
 
-    const float *V = a.val + blk.v_off;
+    // values in FP32, or (VAL16, BF16 operands only) stored in BF16
+    const float *V = VAL16 ? nullptr : a.val + blk.v_off;
+    const uint16_t *V16 = VAL16 ? a.val16 + blk.v_off : nullptr;
     const uint32_t *M = a.mask;
     const uint32_t *Mb = M + (blk.v_off >> 4);   // the block's code words
     const int ld = blk.ld;
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     // sub-tile ahead; BF16 operands need those registers for the operand
     // conversions, and read the values in place before each product
     constexpr bool kStageV = !BF16;
+    static_assert(!VAL16 || BF16, "BF16 values go with BF16 operands");
     VStage vs;
     if constexpr (kStageV) vstage_load(vs, V, M, blk, m, tile.col, tid);
     const int kt = wq;                            // this wave's k-tile in G_H and G_W
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                         const int i = min(it * 16 + 4 * h4 + r, m - 1);
                         const int j = min((2 * ch + t) * 16 + c16, ncol - 1);
                         const size_t cell = static_cast<size_t>(i) * ld + cl + j;
-                        vv[t][r] = V[cell];
+                        vv[t][r] = VAL16 ? bf16_value(V16[cell]) : V[cell];
                         // v_off, ld and cl are multiples of 16: the cell's code
                         // sits at bits 2 c16 of its word (a clamped cell
                         // reads another code, masked as outside)
@@ -423,16 +426,16 @@ __global__ __launch_bounds__(128) void dense_w_update_kernel(DenseIterArgs a)
     dense_langevin(a, it, 0, blk.row0 + i, k0, xo, gr);
 }
 
-template <bool BF16>
+template <bool BF16, bool VAL16>
 hipError_t launch_tiles(const DenseIterArgs &a, int lik, size_t lds, hipStream_t stream)
 {
     const dim3 grid(static_cast<unsigned>(a.n_tiles)), block(kDenseThreads);
     switch (lik) {
-    case LIK_GAUSS: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAUSS>), grid, block, lds, stream, a); break;
-    case LIK_POISSON: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_POISSON>), grid, block, lds, stream, a); break;
-    case LIK_HALF: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_HALF>), grid, block, lds, stream, a); break;
-    case LIK_GAMMA: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAMMA>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GENERAL>), grid, block, lds, stream, a); break;
+    case LIK_GAUSS: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAUSS, VAL16>), grid, block, lds, stream, a); break;
+    case LIK_POISSON: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_POISSON, VAL16>), grid, block, lds, stream, a); break;
+    case LIK_HALF: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_HALF, VAL16>), grid, block, lds, stream, a); break;
+    case LIK_GAMMA: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GAMMA, VAL16>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((dense_tile_kernel<BF16, LIK_GENERAL, VAL16>), grid, block, lds, stream, a); break;
     }
     return hipGetLastError();
 }
@@ -451,7 +454,11 @@ hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max
 {
     if (a.n_tiles == 0) return hipSuccess;
     const size_t lds = dense_lds_bytes(max_m, a.KS);
-    hipError_t e = bf16 ? launch_tiles<true>(a, lik, lds, stream) : launch_tiles<false>(a, lik, lds, stream);
+    // BF16 values only with BF16 operands; FP32 operands read FP32 values
+    if ((a.val == nullptr) == (a.val16 == nullptr) || (a.val16 != nullptr && !bf16)) return hipErrorInvalidValue;
+    hipError_t e = !bf16        ? launch_tiles<false, false>(a, lik, lds, stream)
+                   : a.val16    ? launch_tiles<true, true>(a, lik, lds, stream)
+                                : launch_tiles<true, false>(a, lik, lds, stream);
     if (e != hipSuccess) return e;
     const int rows_q = max_m * (a.Kp / 4);
     hipLaunchKernelGGL(dense_w_update_kernel, dim3((rows_q + 127) / 128, a.n_blocks), dim3(128), 0, stream, a);
@@ -462,16 +469,21 @@ hipError_t dense_prepare(int max_m, int KS)
 {
     const int lds = static_cast<int>(dense_lds_bytes(max_m, KS));
     const void *fns[] = {
-        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAUSS>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_POISSON>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_HALF>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAMMA>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GENERAL>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAUSS>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_POISSON>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_HALF>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAMMA>),
-        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GENERAL>)};
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAUSS, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_POISSON, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_HALF, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GAMMA, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<false, LIK_GENERAL, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAUSS, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_POISSON, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_HALF, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAMMA, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GENERAL, false>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAUSS, true>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_POISSON, true>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_HALF, true>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GAMMA, true>),
+        reinterpret_cast<const void *>(&dense_tile_kernel<true, LIK_GENERAL, true>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;

@@ -276,7 +276,8 @@ struct DenseIterArgs {
     int32_t n_blocks;
     const DenseTile *tiles;     // the part's tiles
     int32_t n_tiles;
-    const float *val;
+    const float *val;           // FP32 values, or
+    const uint16_t *val16;      // BF16 values (the other pointer is null)
     const uint32_t *mask;       // 2-bit cell codes
     float *w_partial;           // slot_rows x Kp floats per tile
     int32_t slot_rows;          // rows of every W partial slot (the largest padded block height)
@@ -298,13 +299,23 @@ struct DenseIterArgs {
 // Enqueues the dense work of one iteration (tiles with their held-out
 // sums, then the W rows).
 hipError_t launch_dense_iter(const DenseIterArgs &a, int lik, bool bf16, int max_m, hipStream_t stream);
+// A value stored in BF16, widened exactly.
+__host__ __device__ inline float bf16_value(uint16_t b)
+{
+    uint32_t u = static_cast<uint32_t>(b) << 16;
+    float f;
+    __builtin_memcpy(&f, &u, sizeof f);
+    return f;
+}
 // Raises the dynamic LDS limit of the tile kernels for blocks of max_m rows.
 hipError_t dense_prepare(int max_m, int KS);
 size_t dense_lds_bytes(int max_m, int KS);
-// FP64 log-likelihood partials of all dense blocks' training cells.
+// FP64 log-likelihood partials of all dense blocks' training cells (values
+// in val, or in BF16 in val16 when val is null).
 hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
-                               const float *val, const uint32_t *mask, int K, int Kp, double beta, double phi,
-                               double mu_floor, double *partials, int per_block, hipStream_t stream);
+                               const float *val, const uint16_t *val16, const uint32_t *mask, int K, int Kp,
+                               double beta, double phi, double mu_floor, double *partials, int per_block,
+                               hipStream_t stream);
 
 hipError_t launch_philox_blocks(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                 hipStream_t stream);

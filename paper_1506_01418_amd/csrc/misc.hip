@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kLLThreads) void loglik_partial_kernel(
 
 // Same for the training cells of dense blocks: blockIdx.y is the block.
 __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
-    const float *W, const float *Hs, const DenseBlock *blocks, const float *val, const uint32_t *mask, int K,
-    int Kp, double beta, double phi, double mu_floor, double *partials, int per_block)
+    const float *W, const float *Hs, const DenseBlock *blocks, const float *val, const uint16_t *val16,
+    const uint32_t *mask, int K, int Kp, double beta, double phi, double mu_floor, double *partials, int per_block)
 {
     __shared__ double red[kLLThreads];
     const DenseBlock blk = blocks[blockIdx.y];
@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kLLThreads) void dense_loglik_partial_kernel(
             mu += static_cast<double>(a.w) * static_cast<double>(b.w);
         }
         if (beta < 2.0 && mu < mu_floor) mu = mu_floor;
-        acc -= dbeta(static_cast<double>(val[cell]), mu, beta) / phi;
+        const float v = val ? val[cell] : bf16_value(val16[cell]);
+        acc -= dbeta(static_cast<double>(v), mu, beta) / phi;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -180,12 +181,13 @@ hipError_t launch_loglik(const float *W, const float *Hs, const int32_t *row_of_
 }
 
 hipError_t launch_dense_loglik(const float *W, const float *Hs, const DenseBlock *blocks, int n_blocks,
-                               const float *val, const uint32_t *mask, int K, int Kp, double beta, double phi,
-                               double mu_floor, double *partials, int per_block, hipStream_t stream)
+                               const float *val, const uint16_t *val16, const uint32_t *mask, int K, int Kp,
+                               double beta, double phi, double mu_floor, double *partials, int per_block,
+                               hipStream_t stream)
 {
     if (n_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(dense_loglik_partial_kernel, dim3(per_block, n_blocks), dim3(kLLThreads), 0, stream, W,
-                       Hs, blocks, val, mask, K, Kp, beta, phi, mu_floor, partials, per_block);
+                       Hs, blocks, val, val16, mask, K, Kp, beta, phi, mu_floor, partials, per_block);
     return hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ int64_t estimate_bytes(const psgld_job &j)
     b += 8 * cap;                                                  // step-size table
     b += 4 * (B * I + 1) + 32 * j.n_heldout;                       // held-out offsets, cells, sums
     if (!j.row) {
-        b += 4 * (I * J + (kDenseRowAlign - 1) * I * B);           // dense values, rows padded
+        const int64_t vb = j.precision == PSGLD_BF16_DENSE_VALUES ? 2 : 4;
+        b += vb * (I * J + (kDenseRowAlign - 1) * I * B);          // dense values, rows padded
         b += (I * J + (kDenseRowAlign - 1) * I * B) / 4 + 4;        // 2-bit cell codes
         b += (J / 128 + B + 1) * int64_t{kDenseMaxRows} * Kp * 4;  // W partials
         b += (B * B + 1) * 64 + (J / 128 + B + 1) * B * 32;        // block and tile lists

@@ -14,6 +14,18 @@ TOL_FP32 = 1e-5
 TOL_BF16 = 2e-2
 
 
+def bf16_round(x):
+    """FP32 values rounded to the nearest bfloat16 (ties to even), returned
+    as FP32: bfloat16 keeps the sign, the 8 exponent bits and the top 7
+    mantissa bits of an FP32, so the candidates are the value with its low 16
+    bits cleared and the next one up in magnitude."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF
+    up = (low > 0x8000) | ((low == 0x8000) & (((u >> 16) & 1) == 1))
+    r = ((u >> 16) + up.astype(np.uint64)) << 16
+    return r.astype(np.uint32).view(np.float32).reshape(np.shape(x))
+
+
 def oracle_config(wl, flags=0, part_order="cyclic"):
     cfg = oracle.Config(**wl.fit_kwargs())
     cfg.flags = flags

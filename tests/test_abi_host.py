@@ -175,3 +175,30 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(cls), name
         for field, _ in cls._fields_:
             assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_bf16_rounding_of_the_tests_is_nearest_even():
+    """The tests' FP32 -> BF16 rounding (which stands in for the library's
+    on the test side) against the definition: the nearest of all BF16 values,
+    compared in exact FP64 arithmetic, ties to the even mantissa."""
+    from parity import bf16_round
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.standard_normal(20000).astype(np.float32) * np.float32(1e3),
+                        rng.gamma(0.5, 2.0, 20000).astype(np.float32),
+                        np.float32([0.0, 1.0, 255.0, 256.0, 257.0, 3.0e38, 1e-30]),
+                        # exact ties: 1 + 2^-8 (even below), 1 + 3 * 2^-8 (even above)
+                        np.float32([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8)])])
+    r = bf16_round(x)
+    u = x.view(np.uint32)
+    lo = (u & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    hi = ((u & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    xd = x.astype(np.float64)
+    dlo, dhi = np.abs(xd - lo), np.abs(hi - xd)
+    lo_even = ((u >> np.uint32(16)) & np.uint32(1)) == 0
+    want = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo_even, lo, hi)))
+    assert np.array_equal(r.astype(np.float64), want)
+    assert np.all(r.view(np.uint32) & np.uint32(0xFFFF) == 0)
+    assert r[-3] == np.float32(1.0) and r[-2] == np.float32(1.0 + 4 * 2.0 ** -8) and r[-1] == np.float32(-1.0)
+    # integers up to 256 are BF16 values
+    k = np.arange(257, dtype=np.float32)
+    assert np.array_equal(bf16_round(k), k)

@@ -10,7 +10,9 @@ import pytest
 import oracle
 import paper_1506_01418_amd as pkg
 import workloads
-from parity import TOL_BF16, TOL_FP32, oracle_config, step_parity
+import dataclasses
+
+from parity import TOL_BF16, TOL_FP32, bf16_round, oracle_config, step_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -140,14 +142,14 @@ def test_dense_runs_are_bitwise_reproducible():
 
 
 def test_bf16_chain_matches_fp32_heldout_rmse():
-    """BF16 operands against FP32 operands on the same device: the 1025-row
-    Tweedie spectrogram shape (beta = 0.5, K = 64, B = 16) on 4,000 columns,
-    400 iterations with burn-in 200, every block on the dense kernels.  The
-    held-out RMSE of the posterior-mean predictor agrees within 1%, and both
-    improve on the initial factors' RMSE."""
+    """BF16 operands (and BF16-stored values) against FP32 operands on the
+    same device: the 1025-row Tweedie spectrogram shape (beta = 0.5, K = 64,
+    B = 16) on 4,000 columns, 400 iterations with burn-in 200, every block on
+    the dense kernels.  The held-out RMSE of the posterior-mean predictor
+    agrees within 1%, and every chain improves on the initial factors' RMSE."""
     wl = workloads.dense_tweedie(J=4000, T=400, burn_in=200, name="dense_tweedie_1025x4k")
     rmse = {}
-    for prec in (pkg.PSGLD_FP32, pkg.PSGLD_BF16_DENSE):
+    for prec in (pkg.PSGLD_FP32, pkg.PSGLD_BF16_DENSE, pkg.PSGLD_BF16_DENSE_VALUES):
         s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec, dense_min_cols=1)
         s.step(wl.T, wl.eps_a, wl.eps_t0, wl.eps_gamma)
         assert s.num_samples() == wl.T - wl.burn_in
@@ -155,9 +157,53 @@ def test_bf16_chain_matches_fp32_heldout_rmse():
         s.close()
     mu0 = np.einsum("nk,kn->n", wl.W0[wl.hrow].astype(np.float64), wl.H0[:, wl.hcol].astype(np.float64))
     rmse0 = float(np.sqrt(np.mean((wl.hval - mu0) ** 2)))
-    f32, bf16 = rmse[pkg.PSGLD_FP32], rmse[pkg.PSGLD_BF16_DENSE]
-    assert abs(bf16 - f32) / f32 <= 0.01, (f32, bf16)
-    assert f32 < rmse0 and bf16 < rmse0, (f32, bf16, rmse0)
+    f32 = rmse[pkg.PSGLD_FP32]
+    for prec in (pkg.PSGLD_BF16_DENSE, pkg.PSGLD_BF16_DENSE_VALUES):
+        assert abs(rmse[prec] - f32) / f32 <= 0.01, (prec, f32, rmse[prec])
+    assert all(r < rmse0 for r in rmse.values()), (rmse, rmse0)
+
+
+def rounded_values(wl):
+    """The workload with its training values (dense matrix and entries)
+    rounded to BF16; held-out values unchanged."""
+    return dataclasses.replace(wl, dense=bf16_round(wl.dense), val=bf16_round(wl.val))
+
+
+def test_bf16_values_are_rounded_once_to_nearest_even():
+    """PSGLD_BF16_DENSE_VALUES stores the dense blocks' training values in
+    BF16: a chain given FP32 values steps to the same bits as one given the
+    values already rounded to nearest even (by the test's own rounding), and
+    as the BF16-operand chain with FP32 storage of those rounded values, which
+    reads them exactly; with the unrounded values the BF16-operand chain
+    differs, so the rounding is what the storage changes."""
+    wl = dense_case(130, 700, 64, 2, 0.5, seed=12)
+    wr = rounded_values(wl)
+    assert not np.array_equal(wr.val, wl.val)
+    out = {}
+    for name, w, prec in (("v16", wl, pkg.PSGLD_BF16_DENSE_VALUES), ("v16_rounded", wr, pkg.PSGLD_BF16_DENSE_VALUES),
+                          ("v32_rounded", wr, pkg.PSGLD_BF16_DENSE), ("v32", wl, pkg.PSGLD_BF16_DENSE)):
+        s = pkg.PSGLD.from_workload(w, dense=True, precision=prec, dense_min_cols=1)
+        s.step(5, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        out[name] = s.factors() + (s.log_likelihood(),)
+        s.close()
+    for name in ("v16_rounded", "v32_rounded"):
+        assert all(np.array_equal(a, b) for a, b in zip(out["v16"][:2], out[name][:2])), name
+        assert out["v16"][2] == out[name][2], name
+    assert not np.array_equal(out["v16"][0], out["v32"][0])
+
+
+@pytest.mark.parametrize("case", ["cpois_K64_m65", "gauss_K20_ragged"])
+def test_bf16_values_parity(case):
+    """Single steps with BF16-stored values against the oracle on the same
+    rounded values (the chain's data), at the BF16 bound."""
+    wl = {"cpois_K64_m65": lambda: dense_case(130, 1000, 64, 2, 0.5, seed=1),
+          "gauss_K20_ragged": lambda: dense_case(201, 333, 20, 3, 2.0, seed=2, prior="gaussian",
+                                                 mirror=False)}[case]()
+    wr = rounded_values(wl)
+    for steps in (0, 4):
+        err, s = step_parity(wr, steps, dense=True, precision=pkg.PSGLD_BF16_DENSE_VALUES)
+        s.close()
+        assert err <= TOL_BF16, (case, steps, err)
 
 
 @pytest.mark.parametrize("bf16", [False, True])
