@@ -183,7 +183,9 @@ psgld_status psgld_load_coo(psgld_ctx *ctx, int64_t nnz, const int32_t *row,
  * (1 = observed training cell, 0 = missing; NULL = every cell observed).
  * Blocks whose training density exceeds options.dense_threshold are run by
  * the dense kernel, the rest as coordinates (E_ARG if those exceed 2^31 - 64
- * cells).  Same value rules as load_coo. */
+ * cells).  Same value rules as load_coo.  With options.precision =
+ * PSGLD_BF16_DENSE_VALUES the values of the dense-kernel blocks are kept in
+ * BF16 (rounded to nearest even here, once); coordinate blocks keep FP32. */
 psgld_status psgld_load_dense(psgld_ctx *ctx, const float *V, const uint8_t *train_mask);
 
 /* Held-out cells whose posterior-mean prediction is tracked: at every
