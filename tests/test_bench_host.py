@@ -46,6 +46,10 @@ def test_algorithmic_cost_counts_cells_entries_and_extras():
     kept = bench.algorithmic_cost(wl, cells, entries, ho_p, 15, 0)[0]
     assert kept == 4.125 * cells[0] + factors + 16 * 7 + 32 * (wl.I + wl.J) * wl.K
     assert bench.algorithmic_cost(wl, cells, entries, ho_p, 16, 0)[0] == 4.125 * cells[0] + factors + 16 * 7
+    # values stored in BF16: 2 bytes and the training bit per cell
+    assert bench.algorithmic_cost(wl, cells, entries, ho_p, 0, 0, bench.VALUE_BYTES["bf16v"])[0] == \
+        2.125 * cells[0] + factors
+    assert bench.VALUE_BYTES["f32"] == bench.VALUE_BYTES["bf16"] == 4
     # the same matrix in 128-column blocks: every training entry as coordinates
     wl = workloads.dense_tweedie(I=256, J=4096, B=32, name="t")
     dense, cnt, rows, cols = bench.block_placement(wl)
