@@ -339,6 +339,8 @@ def main():
     ap.add_argument("--precision", choices=["f32", "bf16", "bf16v"], default="f32",
                     help="dense-block kernels: FP32 operands, BF16 operands, or BF16 operands with the "
                          "training values also stored in BF16")
+    ap.add_argument("--quads-per-lane", type=int, default=0,
+                    help="with --entries-per-group: use that schedule and kernel variant without tuning")
     ap.add_argument("--entries-per-group", type=int, default=0,
                     help="fix the sparse schedule's entries per group instead of tuning it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -401,10 +403,15 @@ def main():
     chosen, sched_info = None, (None, None, None)
     if runs_sparse:
         t_tune = time.perf_counter()
-        cands = (args.entries_per_group,) if args.entries_per_group > 0 else (16, 32, 64, 128)
-        chosen = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=cands, iters=wl.B)
+        if args.entries_per_group > 0 and args.quads_per_lane > 0:
+            # a fixed schedule (profiling runs: the tuner's timings are perturbed there)
+            s.set_schedule(args.entries_per_group, args.quads_per_lane)
+            chosen, how = args.entries_per_group, "fixed"
+        else:
+            cands = (args.entries_per_group,) if args.entries_per_group > 0 else (16, 32, 64, 128)
+            chosen, how = s.tune(wl.eps_a, wl.eps_t0, wl.eps_gamma, candidates=cands, iters=wl.B), "tuned"
         sched_info = s.schedule_info()
-        print(f"[bench] tuned schedule: {chosen} entries per group, {sched_info[1]} quads per lane, "
+        print(f"[bench] {how} schedule: {chosen} entries per group, {sched_info[1]} quads per lane, "
               f"{sched_info[2]} lanes per group ({time.perf_counter() - t_tune:.1f} s)", file=sys.stderr, flush=True)
     rpc = pieces.get("row_piece", pkg_pieces(wl, "row"))
     cpc = pieces.get("col_piece", pkg_pieces(wl, "col"))
