@@ -202,3 +202,11 @@ def test_bf16_rounding_of_the_tests_is_nearest_even():
     # integers up to 256 are BF16 values
     k = np.arange(257, dtype=np.float32)
     assert np.array_equal(bf16_round(k), k)
+
+
+def test_c_program_builds_against_the_header(tmp_path):
+    """A plain C user of the ABI (tests/c_abi_driver.c) compiles with
+    -Wall -Werror against include/psgld.h and links to the in-tree library."""
+    from c_driver import build_driver
+    exe = build_driver(tmp_path)
+    assert os.access(exe, os.X_OK)
