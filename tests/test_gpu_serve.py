@@ -118,3 +118,30 @@ def test_served_jobs_track_the_oracle():
         assert rmse == pytest.approx(ch.heldout_rmse(wl.hval), rel=1e-4)
         srv.release(jid)
     srv.close()
+
+
+@pytest.mark.parametrize("precision", [pkg.PSGLD_BF16_DENSE, pkg.PSGLD_BF16_DENSE_VALUES])
+def test_served_bf16_dense_jobs_match_runs_alone(precision):
+    """Dense jobs with BF16 operands, and with BF16-stored values, served
+    beside a coordinate job: bitwise the same moments and held-out RMSE as
+    the same runs alone."""
+    wls = [dense_case(128, 300, 16, 2, 0.5, density=0.9, seed=62),
+           dense_case(130, 700, 64, 2, 1.0, density=0.95, seed=63),
+           workloads.random_sparse(400, 300, 9000, 8, 4, beta=1.0, prior="exponential", mirror=True,
+                                   data_seed=64, chain_seed=65)]
+    for wl in wls:
+        wl.burn_in, wl.thin = 12, 2
+    srv = pkg.Server(hbm_budget=8 << 30, max_active=4, iters_per_tick=7)
+    ids = [srv.submit(wl, N_ITER, dense=_is_dense(wl), precision=precision, dense_min_cols=1) for wl in wls]
+    _drain(srv)
+    for jid, wl in zip(ids, wls):
+        assert srv.info(jid)["state"] == pkg.PSGLD_JOB_DONE, srv.error(jid)
+        Wm, Hm, _, _, rmse = srv.result(jid)
+        s = pkg.PSGLD.from_workload(wl, dense=_is_dense(wl), precision=precision, dense_min_cols=1)
+        s.step(N_ITER, wl.eps_a, wl.eps_t0, wl.eps_gamma)
+        aWm, aHm = s.posterior_mean()
+        assert np.array_equal(Wm, aWm) and np.array_equal(Hm, aHm)
+        assert rmse == s.heldout_rmse()
+        s.close()
+        srv.release(jid)
+    srv.close()
