@@ -117,17 +117,18 @@ def test_dense_tweedie_full_size_step_parity(bf16):
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("bf16", [False, True])
-def test_dense_tweedie_1000_iterations_rmse_parity(bf16):
-    """The same workload's full run on the dense kernels, FP32 and BF16
-    operands: held-out RMSE within 1% of the oracle's (FP64) full run, so the
-    BF16 path reaches the plain FP32 result."""
+@pytest.mark.parametrize("precision", ["f32", "bf16", "bf16v"])
+def test_dense_tweedie_1000_iterations_rmse_parity(precision):
+    """The same workload's full run on the dense kernels with FP32 operands,
+    BF16 operands, and BF16 operands on BF16-stored values: held-out RMSE
+    within 1% of the oracle's (FP64, FP32 values) full run, so the BF16
+    paths reach the plain FP32 result."""
     wl = _full("dense_tweedie_1025x100k")
-    prec = pkg.PSGLD_BF16_DENSE if bf16 else pkg.PSGLD_FP32
+    prec = {"f32": pkg.PSGLD_FP32, "bf16": pkg.PSGLD_BF16_DENSE, "bf16v": pkg.PSGLD_BF16_DENSE_VALUES}[precision]
     s = pkg.PSGLD.from_workload(wl, dense=True, precision=prec)
     _long_run_rmse(s, wl, "dense_tweedie_1025x100k")
     s.close()
-    if bf16:
+    if precision == "bf16v":
         _FULL.pop("dense_tweedie_1025x100k")
 
 
